@@ -1,0 +1,357 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests uses the GPU. Each pin is chosen so that a plausible
+mistake in the oracle (a dropped term, a wrong sign, an off-by-one index, a
+transposed operand, a missing diagonal division) fails at least one of them.
+"""
+
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+import synth
+
+
+def exact_int_inverse_check(L_int, X):
+    """L X == I in exact Python integer arithmetic (X must be integral)."""
+    n = L_int.shape[0]
+    Xi = [[int(v) for v in row] for row in X]
+    Li = [[int(v) for v in row] for row in L_int]
+    for i in range(n):
+        for j in range(n):
+            s = sum(Li[i][k] * Xi[k][j] for k in range(n))
+            assert s == (1 if i == j else 0), (i, j, s)
+
+
+# ---------------------------------------------------------------- worked example
+def test_paper_4x4_example_exact(golden):
+    """Section 3 worked example: T^{-1} printed as exact integers."""
+    g = golden("combinatorix_4x4.txt")
+    T, S = g["T"], g["S"]
+    L = T.T.copy()  # lower by transposition (eq. defT remark)
+    X = oracle.tril_inverse(L, unit=True)
+    np.testing.assert_array_equal(X, S.T)
+    Xn = oracle.tril_inverse(L, unit=False)  # diagonal is 1 anyway
+    np.testing.assert_array_equal(Xn, S.T)
+    Xc = oracle.chain_sum_inverse(L, unit=True)
+    np.testing.assert_array_equal(Xc, S.T)
+
+
+def test_hopscotch_listing_h15(golden):
+    """Example examplek15: H(1,5) has the 8 listed chains; the count is 2^(5-1-1)."""
+    seqs = golden("hopscotch_h15.txt")
+    assert len(seqs) == 8 == oracle.chain_count(1, 5)
+    assert len({tuple(s) for s in seqs}) == 8
+    for s in seqs:
+        assert s[0] == 1 and s[-1] == 5 and all(a < b for a, b in zip(s, s[1:]))
+
+
+@pytest.mark.parametrize("a,b", [(1, 2), (1, 3), (2, 7), (5, 8), (3, 15)])
+def test_chain_count_closed_form(a, b):
+    """Proposition corrTranlation: |H(a,b)| = 2^(b-a-1); Corollary Translation:
+    the count depends on b - a only."""
+    assert oracle.chain_count(a, b) == 2 ** (b - a - 1)
+    assert oracle.chain_count(a + 4, b + 4) == oracle.chain_count(a, b)
+
+
+def test_chain_sum_matches_listed_sequences(golden):
+    """S_15 of a 5x5 unit upper T from the eight listed chains of H(1,5), with
+    sign (-1)^(len-1) and the product over consecutive chain pairs
+    (Theorem Combinatorix), against the oracle's enumeration."""
+    seqs = golden("hopscotch_h15.txt")
+    rng = np.random.default_rng(11)
+    T = np.triu(rng.integers(-4, 5, size=(5, 5)).astype(np.float64), 1) + np.eye(5)
+    s15 = 0.0
+    for s in seqs:
+        p = 1.0
+        for a, b in zip(s, s[1:]):
+            p *= T[a - 1, b - 1]
+        s15 += (-1.0) ** (len(s) - 1) * p
+    X = oracle.chain_sum_inverse(T.T.copy(), unit=True)
+    assert X[4, 0] == s15
+    assert s15 == np.linalg.inv(T)[0, 4].round()
+
+
+# ---------------------------------------------------------------- brute force
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+@pytest.mark.parametrize("unit", [False, True])
+def test_chain_sum_vs_recurrence(n, unit):
+    """Theorem Combinatorix by enumeration (n <= 8) against the recurrence."""
+    L = synth.lower_triangular(n, seed=100 + n)
+    L[np.tril_indices(n, -1)] *= n  # O(1) off-diagonals so every chain matters
+    Xr = oracle.tril_inverse(L, unit=unit)
+    Xc = oracle.chain_sum_inverse(L, unit=unit)
+    np.testing.assert_allclose(Xc, Xr, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [4, 7])
+def test_chain_sum_exact_rational(n):
+    """Integer non-unit input: chain sum equals the exact rational inverse."""
+    rng = np.random.default_rng(n)
+    L = np.tril(rng.integers(-3, 4, size=(n, n)), -1).astype(np.float64)
+    d = rng.choice([-2, -1, 1, 2, 4], size=n).astype(np.float64)
+    L[np.arange(n), np.arange(n)] = d
+    # exact inverse by Fraction forward substitution of L x = e_j
+    exact = [[Fraction(0)] * n for _ in range(n)]
+    for j in range(n):
+        x = [Fraction(0)] * n
+        for i in range(n):
+            rhs = Fraction(1 if i == j else 0) - sum(Fraction(int(L[i, k])) * x[k] for k in range(i))
+            x[i] = rhs / Fraction(int(L[i, i]))
+        for i in range(n):
+            exact[i][j] = x[i]
+    Xc = oracle.chain_sum_inverse(L)
+    Xr = oracle.tril_inverse(L)
+    ex = np.array([[float(v) for v in row] for row in exact])
+    np.testing.assert_allclose(Xc, ex, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(Xr, ex, rtol=1e-15, atol=0)
+
+
+# ---------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("n", [1, 2, 9, 64, 300])
+def test_minus_one_bidiagonal_gives_all_ones(n):
+    """Unit bidiagonal with -1 sub-diagonal: inverse is the all-ones lower triangle."""
+    L = np.eye(n)
+    L[np.arange(1, n), np.arange(n - 1)] = -1.0
+    X = oracle.tril_inverse(L)
+    np.testing.assert_array_equal(X, np.tril(np.ones((n, n))))
+    if n <= 9:
+        np.testing.assert_array_equal(oracle.chain_sum_inverse(L), np.tril(np.ones((n, n))))
+
+
+@pytest.mark.parametrize("n", [3, 10, 40])
+def test_all_minus_one_gives_powers_of_two(n):
+    """Strict lower all -1: X_ij = 2^(i-j-1) for i > j (one per chain, all signs +)."""
+    L = np.eye(n) - np.tril(np.ones((n, n)), -1)
+    X = oracle.tril_inverse(L, unit=True)
+    i, j = np.indices((n, n))
+    expect = np.where(i > j, 2.0 ** (i - j - 1), np.where(i == j, 1.0, 0.0))
+    np.testing.assert_array_equal(X, expect)
+    if n <= 10:
+        np.testing.assert_array_equal(oracle.chain_sum_inverse(L, unit=True), expect)
+
+
+@pytest.mark.parametrize("a,n", [(0.5, 60), (3.0, 20), (-2.0, 30)])
+def test_geometric_bidiagonal(a, n):
+    """L = I - a * subdiag: X_ij = a^(i-j)."""
+    L = np.eye(n)
+    L[np.arange(1, n), np.arange(n - 1)] = -a
+    X = oracle.tril_inverse(L)
+    i, j = np.indices((n, n))
+    expect = np.where(i >= j, a ** np.maximum(i - j, 0), 0.0)
+    np.testing.assert_array_equal(X, expect)
+
+
+def test_toeplitz_preserved():
+    """Corollary Translation: chain sets of each diagonal band are shifts of
+    each other, so a Toeplitz lower matrix has a Toeplitz inverse."""
+    n = 48
+    c = synth.uniform01(5, np.arange(n)) - 0.5
+    c[0] = 1.5
+    i, j = np.indices((n, n))
+    L = np.where(i >= j, c[np.clip(i - j, 0, n - 1)], 0.0)
+    X = oracle.tril_inverse(L)
+    for k in range(n):
+        band = np.diagonal(X, offset=-k)
+        np.testing.assert_allclose(band, band[0], rtol=1e-12, atol=1e-15)
+
+
+def test_integer_closure_exact():
+    """Corollary after the worked example: integer unit lower -> integer inverse."""
+    n = 14
+    L = synth.integer_unit_lower(n, seed=9)
+    X = oracle.tril_inverse(L, unit=True)
+    assert np.all(X == np.round(X))
+    assert np.max(np.abs(X)) < 2.0 ** 50
+    exact_int_inverse_check(L, X)
+
+
+# ---------------------------------------------------------------- library special case
+@pytest.mark.parametrize("n,seed", [(64, 1), (200, 2), (257, 3)])
+def test_matches_scipy_triangular_solve(n, seed):
+    L = synth.lower_triangular(n, seed)
+    X = oracle.tril_inverse(L)
+    ref = scipy.linalg.solve_triangular(L, np.eye(n), lower=True)
+    np.testing.assert_allclose(X, ref, rtol=1e-12, atol=1e-15)
+
+
+def test_unit_flag_ignores_stored_diagonal():
+    n = 50
+    L = synth.lower_triangular(n, 4)
+    Lu = L.copy()
+    Lu[np.arange(n), np.arange(n)] = 1.0
+    ref = scipy.linalg.solve_triangular(Lu, np.eye(n), lower=True, unit_diagonal=True)
+    np.testing.assert_allclose(oracle.tril_inverse(L, unit=True), ref, rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------- invariants
+def test_invariants():
+    n = 300
+    L = synth.lower_triangular(n, 1)
+    X = oracle.tril_inverse(L)
+    assert np.all(np.triu(X, 1) == 0.0)
+    np.testing.assert_array_equal(np.diag(X), 1.0 / np.diag(L))
+    r = oracle.residuals(L, X)
+    assert r["rel_lx"] < 1e-16 * 10 and r["rel_xl"] < 1e-16 * 10
+    # numpy's own product as an outside check of both residual directions
+    I = np.eye(n)
+    assert np.linalg.norm(L @ X - I) / (np.linalg.norm(L) * np.linalg.norm(X)) < 1e-15
+    assert np.linalg.norm(X @ L - I) / (np.linalg.norm(L) * np.linalg.norm(X)) < 1e-15
+
+
+def test_principal_blocks_bitwise():
+    """X[:k,:k] = inv(L[:k,:k]) and X[k:,k:] = inv(L[k:,k:]) exactly: each entry
+    only uses entries of L inside the block."""
+    n = 70
+    L = synth.lower_triangular(n, 6)
+    X = oracle.tril_inverse(L)
+    for k in (1, 17, 35, 69):
+        np.testing.assert_array_equal(X[:k, :k], oracle.tril_inverse(L[:k, :k]))
+        np.testing.assert_array_equal(X[k:, k:], oracle.tril_inverse(L[k:, k:]))
+
+
+def test_power_of_two_scaling_bitwise():
+    n = 64
+    L = synth.lower_triangular(n, 7)
+    X = oracle.tril_inverse(L)
+    np.testing.assert_array_equal(oracle.tril_inverse(L * 8.0), X / 8.0)
+
+
+def test_upper_garbage_ignored():
+    n = 90
+    L = synth.lower_triangular(n, 8)
+    Lg = synth.lower_triangular(n, 8, upper_garbage=True)
+    assert np.any(np.triu(Lg, 1) != 0)
+    np.testing.assert_array_equal(oracle.tril_inverse(Lg), oracle.tril_inverse(L))
+
+
+def test_columns_match_full():
+    n = 120
+    L = synth.lower_triangular(n, 9)
+    X = oracle.tril_inverse(L)
+    cols = [0, 1, 59, 119]
+    np.testing.assert_array_equal(oracle.tril_inverse_columns(L, cols), X[:, cols])
+
+
+def test_singular_reports_first_zero_diagonal():
+    n = 20
+    L = synth.lower_triangular(n, 10)
+    L[5, 5] = 0.0
+    L[12, 12] = 0.0
+    with pytest.raises(oracle.SingularMatrix) as e:
+        oracle.tril_inverse(L)
+    assert e.value.index == 6
+    # unit flag: the stored diagonal is not read, so no error
+    oracle.tril_inverse(L, unit=True)
+
+
+# ---------------------------------------------------------------- residual metric
+def test_residual_planted_perturbation():
+    """X = exact inverse + delta e_p e_q^T: ||LX - I||_F = |delta| ||L(:,p)||_2 and
+    ||XL - I||_F = |delta| ||L(q,:)||_2."""
+    n = 12
+    L = synth.integer_unit_lower(n, seed=3)
+    X = oracle.tril_inverse(L, unit=True)
+    r0 = oracle.residuals(L, X)
+    assert r0["lx"] == 0.0 and r0["xl"] == 0.0
+    p, q, delta = 7, 2, 2.0 ** -10
+    Xp = X.copy()
+    Xp[p, q] += delta
+    r = oracle.residuals(L, Xp)
+    assert r["lx"] == pytest.approx(delta * np.linalg.norm(L[:, p]), rel=1e-12)
+    assert r["xl"] == pytest.approx(delta * np.linalg.norm(L[q, :]), rel=1e-12)
+    # a non-zero in the strict upper part of X is seen as well
+    Xu = X.copy()
+    Xu[1, 5] = delta
+    assert oracle.residuals(L, Xu)["lx"] == pytest.approx(delta * np.linalg.norm(L[:, 1]), rel=1e-12)
+    cols = oracle.residual_columns(L, Xp, np.arange(n))
+    assert np.sqrt(cols.sum()) == pytest.approx(r["lx"], rel=1e-12)
+    assert cols[q] == pytest.approx(r["lx"] ** 2, rel=1e-12)
+
+
+# ---------------------------------------------------------------- factored inverse
+def test_skul_printed_example(golden):
+    """Section 6: from the printed L and U, K = L^{-1} and S = U^{-1} match the
+    printed values to the four printed decimals; A * (S K) = I to the precision
+    of the printed A."""
+    g = golden("skul_5x5.txt")
+    A, U, L, S, K = g["A"], g["U"], g["L"], g["S"], g["K"]
+    np.testing.assert_allclose(L @ U, A, atol=2e-4)  # fixture sanity: L U = A
+    Linv, Uinv, Ainv = oracle.factored_inverse(L, U, l_unit=False, u_unit=True)
+    np.testing.assert_allclose(Linv, K, atol=1e-4)
+    np.testing.assert_allclose(Uinv, S, atol=1e-4)
+    np.testing.assert_allclose(A @ Ainv, np.eye(5), atol=1e-3)
+    np.testing.assert_allclose(Ainv, S @ K, atol=2e-4)
+
+
+def test_factored_inverse_identities():
+    n = 80
+    L = synth.lower_triangular(n, 3, unit=True)
+    U = synth.upper_triangular(n, 4)
+    Linv, Uinv, Ainv = oracle.factored_inverse(L, U, l_unit=True, u_unit=False)
+    I = np.eye(n)
+    assert np.max(np.abs(L @ Linv - I)) < 1e-14
+    assert np.max(np.abs(U @ Uinv - I)) < 1e-14
+    assert np.all(np.tril(Uinv, -1) == 0) and np.all(np.triu(Linv, 1) == 0)
+    assert np.max(np.abs((L @ U) @ Ainv - I)) < 1e-13
+    np.testing.assert_allclose(Uinv, scipy.linalg.solve_triangular(U, I, lower=False), rtol=1e-12,
+                               atol=1e-15)
+
+
+# ---------------------------------------------------------------- gradient
+def _loss(L, W):
+    return float(np.sum(W * oracle.tril_inverse(L)))
+
+
+def test_backward_finite_differences():
+    """grad of f(L) = sum(W .* L^{-1}) against FP64 central differences, h = 1e-6."""
+    n = 16
+    L = synth.lower_triangular(n, 7)
+    W = synth.normal(n, n, seed=7)
+    g = oracle.tril_inverse_backward(L, W)
+    h = 1e-6
+    fd = np.zeros((n, n))
+    for i in range(n):
+        for j in range(i + 1):
+            Lp = L.copy()
+            Lm = L.copy()
+            Lp[i, j] += h
+            Lm[i, j] -= h
+            fd[i, j] = (_loss(Lp, W) - _loss(Lm, W)) / (2 * h)
+    assert np.all(np.triu(g, 1) == 0)
+    assert np.linalg.norm(fd - g) / np.linalg.norm(g) < 1e-7
+
+
+def test_backward_closed_forms():
+    # 1x1: d(w / l)/dl = -w / l^2
+    g = oracle.tril_inverse_backward(np.array([[2.0]]), np.array([[3.0]]))
+    assert g[0, 0] == -3.0 / 4.0
+    # 2x2: X = [[1/a, 0], [-c/(ab), 1/b]]
+    a, c, b = 1.5, 0.25, -2.0
+    w11, w12, w21, w22 = 0.5, 9.0, -1.25, 2.0
+    L = np.array([[a, 0.0], [c, b]])
+    W = np.array([[w11, w12], [w21, w22]])
+    g = oracle.tril_inverse_backward(L, W)
+    np.testing.assert_allclose(g[0, 0], -w11 / a**2 + w21 * c / (a**2 * b), rtol=1e-15)
+    np.testing.assert_allclose(g[1, 0], -w21 / (a * b), rtol=1e-15)
+    np.testing.assert_allclose(g[1, 1], -w22 / b**2 + w21 * c / (a * b**2), rtol=1e-15)
+    assert g[0, 1] == 0.0
+
+
+def test_backward_linear_in_g_and_rows():
+    n = 24
+    L = synth.lower_triangular(n, 12)
+    G1 = synth.normal(n, n, 1)
+    G2 = synth.normal(n, n, 2)
+    g = oracle.tril_inverse_backward(L, G1 + 2.0 * G2)
+    np.testing.assert_allclose(g, oracle.tril_inverse_backward(L, G1) + 2.0 * oracle.tril_inverse_backward(L, G2),
+                               rtol=1e-12, atol=1e-13)
+    # only tril(G) matters (X lower => the strict upper of G drops out)
+    np.testing.assert_allclose(oracle.tril_inverse_backward(L, np.tril(G1)), oracle.tril_inverse_backward(L, G1),
+                               rtol=1e-12, atol=1e-14)
+    rows = [0, 5, 23]
+    np.testing.assert_array_equal(oracle.tril_inverse_backward_rows(L, G1, rows),
+                                  oracle.tril_inverse_backward(L, G1)[rows])
