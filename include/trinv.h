@@ -1,0 +1,201 @@
+/*
+ * trinv.h -- C ABI of the MI355X (gfx950) triangular-inverse library.
+ *
+ * The operation (Riahi, "Combinatorial and Recurrent Approaches for Efficient
+ * Matrix Inversion", 2023): invert a non-singular triangular matrix
+ * (Section 2, eq. defT; the paper states the unit upper case and obtains the
+ * lower case by transposition and the non-unit case through a diagonal
+ * factor R = D T, Section 4) by recursive 2x2 block splitting (Section 4.1,
+ * algorithm COMBRIT with beta = 2):
+ *
+ *     [ A  0 ]^-1   [  A^-1           0    ]
+ *     [ C  B ]    = [ -B^-1 C A^-1    B^-1 ]
+ *
+ * with the diagonal blocks inverted recursively and the smallest ("leaf")
+ * blocks inverted by the column recurrence CRIT (Section 4.2; any leaf method
+ * is allowed, Remark rmkCOMBRIT). The off-diagonal block is formed as
+ * T = C * A^-1 followed by X21 = -B^-1 * T, i.e. the product with the inverted
+ * diagonal block first (COMBRIT's B_ij = iD_ii A_ij, then iA_ij = iB_ij iD_jj,
+ * transposed to the lower case).
+ *
+ * Conventions shared by every call:
+ *   - All matrix pointers are DEVICE pointers owned by the caller; the
+ *     library never allocates, frees or keeps them. Matrices are row-major;
+ *     element (i, j) of A with leading dimension lda is A[i * lda + j].
+ *   - Only the lower triangle (j <= i) of an input L is read; the strict
+ *     upper part is ignored whatever it holds. With opts->unit_diag the
+ *     diagonal is taken as 1 and not read.
+ *   - The output X = L^-1 is written in full: lower triangle = the inverse,
+ *     strict upper part = +0.0.
+ *   - X must not overlap L (or any other input).
+ *   - Every call is ordered on the given stream (a hipStream_t; NULL means
+ *     the legacy default stream) and returns without waiting for the GPU
+ *     unless opts->blocking is set, or the mode needs a host decision (the
+ *     refinement loop reads one 8-byte norm per iteration).
+ *   - The workspace is caller-owned device memory of at least
+ *     trinv_workspace_bytes(...) bytes, 256-byte aligned.
+ *   - n == 0 (or batch == 0) is a no-op returning TRINV_OK.
+ *
+ * Errors: a negative size, ld < n, a NULL required pointer, overlapping input
+ * and output, or an unsupported mode returns TRINV_ERR_ARG /
+ * TRINV_ERR_UNSUPPORTED before anything is launched. A too-small workspace
+ * returns TRINV_ERR_WORKSPACE. A HIP launch or runtime error returns
+ * TRINV_ERR_HIP. An exactly zero diagonal entry (the paper stops only on an
+ * exact zero pivot, algorithms SQR/SKUL) is reported as TRINV_ERR_SINGULAR
+ * with info->first_bad_index = its 1-based index when the call waits for the
+ * GPU (opts->blocking or the refine modes); X is unspecified then.
+ */
+#ifndef TRINV_H
+#define TRINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A hipStream_t passed as an opaque pointer. */
+typedef void *trinv_stream_t;
+
+typedef enum {
+  /* FP64 storage, FP64 leaves, FP64 MFMA products. */
+  TRINV_F64 = 0,
+  /* FP32 storage, FP32 leaves, FP32 MFMA products. */
+  TRINV_F32 = 1,
+  /* FP64 storage and FP64 leaves; off-diagonal products on BF16 MFMA with
+   * FP32 accumulation; then Newton-Schulz refinement X <- X + X (I - L X)
+   * (which keeps X lower triangular) until the relative residual
+   * ||L X - I||_F / (||L||_F ||X||_F) <= opts->tol. The residual is
+   * assembled, stored and reduced in FP64; its O(n^3) strictly-lower product
+   * runs on split BF16 slices, so the whole residual stays accurate to far
+   * below the tolerance. */
+  TRINV_BF16_REFINE = 2,
+  /* As TRINV_BF16_REFINE with FP16 slices (power-of-two scaled rows and
+   * columns to keep them in FP16 range). */
+  TRINV_F16_REFINE = 3
+} trinv_mode;
+
+typedef enum {
+  TRINV_OK = 0,
+  TRINV_ERR_ARG = 1,
+  TRINV_ERR_SINGULAR = 2,
+  TRINV_ERR_NONFINITE = 3,
+  TRINV_ERR_NOT_CONVERGED = 4,
+  TRINV_ERR_HIP = 5,
+  TRINV_ERR_UNSUPPORTED = 6,
+  TRINV_ERR_WORKSPACE = 7
+} trinv_status;
+
+typedef struct {
+  int32_t leaf;      /* leaf block order; 0 = the mode's default (tuned) */
+  int32_t unit_diag; /* 1: the diagonal is taken as 1 and not read */
+  int32_t upper;     /* 1: the input is UPPER triangular; the upper inverse is
+                        returned (computed through the transposed view) */
+  int32_t max_iter;  /* refine modes: most Newton-Schulz corrections (default 4) */
+  double tol;        /* refine modes: target relative residual (default 1e-12) */
+  int32_t blocking;  /* 1: wait for the GPU and fill *info (status, residual) */
+  int32_t check;     /* 1 (with blocking): also compute the FP64 relative
+                        residual of the result into info->rel_residual */
+} trinv_opts;
+
+typedef struct {
+  double rel_residual;     /* ||L X - I||_F / (||L||_F ||X||_F), or -1 if not computed */
+  double resid_error_bound;/* refine modes: bound on the error of rel_residual */
+  int32_t iterations;      /* refine modes: corrections applied */
+  int64_t first_bad_index; /* 1-based index of the first zero diagonal, 0 = none */
+} trinv_info;
+
+/* Fills *opts with the defaults (leaf 0, unit_diag 0, upper 0, max_iter 4,
+ * tol 1e-12, blocking 0, check 0). Passing opts == NULL to any call means
+ * these defaults. */
+void trinv_default_opts(trinv_opts *opts);
+
+/* Human-readable name of a status code (static storage). */
+const char *trinv_status_string(int status);
+
+/* Bytes of workspace trinv_tril_inverse needs for (mode, n, opts). */
+size_t trinv_workspace_bytes(int mode, int64_t n, const trinv_opts *opts);
+
+/*
+ * X = L^-1 for one n x n triangular matrix (lower by default).
+ * mode: a trinv_mode. L: device, FP64 for F64/BF16_REFINE/F16_REFINE, FP32
+ * for F32; ldl >= n. X: device, same element type, ldx >= n, written in
+ * full. ws/ws_bytes: workspace (see trinv_workspace_bytes). info: nullable.
+ * Returns a trinv_status.
+ */
+int trinv_tril_inverse(int mode, int64_t n, const void *L, int64_t ldl, void *X, int64_t ldx,
+                       const trinv_opts *opts, void *ws, size_t ws_bytes, trinv_stream_t stream,
+                       trinv_info *info);
+
+/* Bytes of workspace trinv_tril_inverse_batched needs for this batch
+ * (n_host: host array of the batch sizes, used for planning only). */
+size_t trinv_batched_workspace_bytes(int mode, int64_t batch, const int32_t *n_host,
+                                     const trinv_opts *opts);
+
+/*
+ * X_i = L_i^-1 for `batch` independent lower-triangular matrices of uneven
+ * order, packed back to back (the paper's parallel remark: independent
+ * diagonal blocks can be inverted concurrently, Section 4.1 complexity
+ * analysis). mode: TRINV_F32 or TRINV_F64.
+ *   n_host / n_dev: the orders n_i (host copy for planning, device copy read
+ *     by the kernels; identical contents), 1 <= n_i <= 1024.
+ *   off_host / off_dev: int64 element offsets of matrix i in L_packed and
+ *     X_packed; matrix i is dense n_i x n_i row-major with leading dimension
+ *     n_i. Regions must not overlap.
+ *   status_dev: device int32[batch]; status_dev[i] = 0, or the 1-based index
+ *     of the first zero diagonal of matrix i.
+ * The whole batch runs in one persistent kernel launch; the plan (work
+ * order, tile and leaf sizes) is chosen on the host from n_host and cached.
+ * Returns a trinv_status (TRINV_ERR_SINGULAR only with opts->blocking).
+ */
+int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t *n_host, const int32_t *n_dev,
+                               const int64_t *off_host, const int64_t *off_dev, const void *L_packed,
+                               void *X_packed, int32_t *status_dev, const trinv_opts *opts, void *ws,
+                               size_t ws_bytes, trinv_stream_t stream);
+
+/*
+ * Adjoint of X = L^-1 for a strided batch of lower-triangular matrices:
+ *     gradL = -tril(X^T G X^T)
+ * (from dX = -X dL X; not part of the paper). X is the forward's output
+ * (lower, strict upper read as zero), G the gradient with respect to X (only
+ * its lower triangle contributes), gradL the gradient with respect to the
+ * lower entries of L (strict upper written as 0). mode: TRINV_F32 or
+ * TRINV_F64. Matrix b starts at element b * stride of each array; all have
+ * leading dimension n. ws: workspace of trinv_backward_workspace_bytes.
+ */
+size_t trinv_backward_workspace_bytes(int mode, int64_t batch, int64_t n);
+int trinv_tril_inverse_backward(int mode, int64_t batch, int64_t n, const void *X, const void *G,
+                                void *gradL, int64_t stride, void *ws, size_t ws_bytes,
+                                trinv_stream_t stream);
+
+/*
+ * Factored inverse from given triangular factors A = L U (Section 5,
+ * algorithm SKUL's output statement: with S = U^-1 and K = L^-1,
+ * S K = A^-1): Linv = L^-1 (lower), Uinv = U^-1 (upper, computed through the
+ * transposed view of U), and, if Ainv != NULL, Ainv = Uinv * Linv (dense).
+ * l_unit / u_unit: take that factor's diagonal as 1. mode: TRINV_F64 or
+ * TRINV_F32. All leading dimensions are n. ws: at least
+ * trinv_factored_workspace_bytes bytes. info: nullable.
+ */
+size_t trinv_factored_workspace_bytes(int mode, int64_t n, const trinv_opts *opts);
+int trinv_factored_inverse(int mode, int64_t n, const void *L, int32_t l_unit, const void *U,
+                           int32_t u_unit, void *Linv, void *Uinv, void *Ainv, const trinv_opts *opts,
+                           void *ws, size_t ws_bytes, trinv_stream_t stream, trinv_info *info);
+
+/*
+ * Measurement helper (not part of the method): FP64 relative residual of a
+ * candidate inverse, computed on the GPU with FP64 MFMA products:
+ *   out_host[0] = ||L X - I||_F, [1] = ||tril(L)||_F, [2] = ||X||_F.
+ * mode selects the element type of L and X (F64 or F32; the arithmetic is
+ * FP64 in both cases). Waits for the GPU. ws: trinv_residual_workspace_bytes.
+ */
+size_t trinv_residual_workspace_bytes(int mode, int64_t n);
+int trinv_residual(int mode, int64_t n, const void *L, int64_t ldl, const void *X, int64_t ldx,
+                   void *ws, size_t ws_bytes, trinv_stream_t stream, double *out_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRINV_H */

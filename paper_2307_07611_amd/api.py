@@ -1,0 +1,202 @@
+"""PyTorch-facing wrappers of libtrinv (argument marshalling only).
+
+PyTorch supplies device memory (outputs and workspaces) and the current HIP
+stream; every step of the computation runs in the library's HIP kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+_DT = {torch.float64: "f64", torch.float32: "f32"}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise ValueError("expected CUDA (HIP) tensors")
+
+
+def _mode_for(t: torch.Tensor, mode):
+    if mode is None:
+        if t.dtype not in _DT:
+            raise ValueError(f"unsupported dtype {t.dtype}")
+        mode = _DT[t.dtype]
+    m = _lib.MODES[mode]
+    want = torch.float32 if m == _lib.F32 else torch.float64
+    if t.dtype != want:
+        raise ValueError(f"mode {mode} needs {want} inputs, got {t.dtype}")
+    return m
+
+
+def _opts(leaf=0, unit_diag=False, upper=False, max_iter=4, tol=1e-12, blocking=True, check=False):
+    o = _lib.Opts()
+    _lib.load().trinv_default_opts(ctypes.byref(o))
+    o.leaf, o.unit_diag, o.upper = int(leaf), int(unit_diag), int(upper)
+    o.max_iter, o.tol, o.blocking, o.check = int(max_iter), float(tol), int(blocking), int(check)
+    return o
+
+
+def _workspace(nbytes: int, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _info_dict(info: _lib.Info) -> dict:
+    return {"rel_residual": info.rel_residual, "resid_error_bound": info.resid_error_bound,
+            "iterations": info.iterations, "first_bad_index": info.first_bad_index}
+
+
+def tril_inverse(L: torch.Tensor, mode=None, *, leaf=0, unit_diag=False, upper=False, max_iter=4, tol=1e-12,
+                 blocking=True, check=False, out=None, workspace=None, return_info=False):
+    """X = L^-1 for one triangular matrix (lower; ``upper=True`` for upper)."""
+    _check_dev(L)
+    if L.dim() != 2 or L.shape[0] != L.shape[1] or L.stride(1) != 1:
+        raise ValueError("L must be a square matrix with unit column stride")
+    m = _mode_for(L, mode)
+    n = L.shape[0]
+    X = out if out is not None else torch.empty((n, n), dtype=L.dtype, device=L.device)
+    lib = _lib.load()
+    o = _opts(leaf, unit_diag, upper, max_iter, tol, blocking, check)
+    nbytes = lib.trinv_workspace_bytes(m, n, ctypes.byref(o))
+    ws = workspace if workspace is not None else _workspace(nbytes, L.device)
+    info = _lib.Info()
+    st = lib.trinv_tril_inverse(m, n, L.data_ptr(), L.stride(0), X.data_ptr(), X.stride(0), ctypes.byref(o),
+                                ws.data_ptr(), ws.numel(), _stream(), ctypes.byref(info))
+    if st != _lib.OK:
+        raise _lib.TrinvError(st, "trinv_tril_inverse", _info_dict(info))
+    return (X, _info_dict(info)) if return_info else X
+
+
+def workspace_bytes(n: int, mode="f64", **kw) -> int:
+    return int(_lib.load().trinv_workspace_bytes(_lib.MODES[mode], n, ctypes.byref(_opts(**kw))))
+
+
+def residual(L: torch.Tensor, X: torch.Tensor) -> dict:
+    """FP64 ||LX - I||_F, ||L||_F, ||X||_F computed on the GPU (FP64 MFMA)."""
+    _check_dev(L, X)
+    m = _mode_for(L, None)
+    n = L.shape[0]
+    lib = _lib.load()
+    ws = _workspace(lib.trinv_residual_workspace_bytes(m, n), L.device)
+    out = (ctypes.c_double * 3)()
+    st = lib.trinv_residual(m, n, L.data_ptr(), L.stride(0), X.data_ptr(), X.stride(0), ws.data_ptr(), ws.numel(),
+                            _stream(), out)
+    if st != _lib.OK:
+        raise _lib.TrinvError(st, "trinv_residual")
+    r = {"lx": out[0], "norm_l": out[1], "norm_x": out[2]}
+    r["rel"] = r["lx"] / (r["norm_l"] * r["norm_x"]) if r["norm_l"] * r["norm_x"] else 0.0
+    return r
+
+
+def tril_inverse_backward(X: torch.Tensor, G: torch.Tensor) -> torch.Tensor:
+    """-tril(X^T G X^T) for a matrix or a batch (leading dimension) of matrices."""
+    _check_dev(X, G)
+    squeeze = X.dim() == 2
+    Xb = X.unsqueeze(0) if squeeze else X
+    Gb = (G.unsqueeze(0) if squeeze else G).contiguous()
+    Xb = Xb.contiguous()
+    batch, n = Xb.shape[0], Xb.shape[-1]
+    m = _mode_for(Xb, None)
+    grad = torch.empty_like(Xb)
+    lib = _lib.load()
+    ws = _workspace(lib.trinv_backward_workspace_bytes(m, batch, n), X.device)
+    st = lib.trinv_tril_inverse_backward(m, batch, n, Xb.data_ptr(), Gb.data_ptr(), grad.data_ptr(), n * n,
+                                         ws.data_ptr(), ws.numel(), _stream())
+    if st != _lib.OK:
+        raise _lib.TrinvError(st, "trinv_tril_inverse_backward")
+    return grad[0] if squeeze else grad
+
+
+def factored_inverse(L: torch.Tensor, U: torch.Tensor, *, l_unit=False, u_unit=False, want_ainv=True, leaf=0,
+                     blocking=True):
+    """(Linv, Uinv, Ainv) with A = L U; Ainv = Uinv Linv (None if not wanted)."""
+    _check_dev(L, U)
+    L = L.contiguous()
+    U = U.contiguous()
+    m = _mode_for(L, None)
+    n = L.shape[0]
+    Linv = torch.empty_like(L)
+    Uinv = torch.empty_like(U)
+    Ainv = torch.empty_like(L) if want_ainv else None
+    lib = _lib.load()
+    o = _opts(leaf=leaf, blocking=blocking)
+    ws = _workspace(lib.trinv_factored_workspace_bytes(m, n, ctypes.byref(o)), L.device)
+    info = _lib.Info()
+    st = lib.trinv_factored_inverse(m, n, L.data_ptr(), int(l_unit), U.data_ptr(), int(u_unit), Linv.data_ptr(),
+                                    Uinv.data_ptr(), Ainv.data_ptr() if Ainv is not None else None,
+                                    ctypes.byref(o), ws.data_ptr(), ws.numel(), _stream(), ctypes.byref(info))
+    if st != _lib.OK:
+        raise _lib.TrinvError(st, "trinv_factored_inverse", _info_dict(info))
+    return Linv, Uinv, Ainv
+
+
+def tril_inverse_batched(L_packed: torch.Tensor, sizes, offsets=None, mode=None, *, blocking=True, leaf=0,
+                         out=None, workspace=None, n_dev=None, off_dev=None):
+    """Inverse of every matrix of a packed batch (dense n_i x n_i blocks at
+    element offsets ``offsets``); returns (X_packed, status per matrix)."""
+    _check_dev(L_packed)
+    import numpy as np
+
+    sizes_np = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
+    if offsets is None:
+        offsets = np.zeros(len(sizes_np), dtype=np.int64)
+        if len(sizes_np) > 1:
+            offsets[1:] = np.cumsum(sizes_np[:-1].astype(np.int64) ** 2)
+    off_np = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    m = _mode_for(L_packed, mode)
+    batch = len(sizes_np)
+    dev = L_packed.device
+    if n_dev is None:
+        n_dev = torch.from_numpy(sizes_np).to(dev)
+    if off_dev is None:
+        off_dev = torch.from_numpy(off_np).to(dev)
+    X = out if out is not None else torch.empty_like(L_packed)
+    status = torch.empty(batch, dtype=torch.int32, device=dev)
+    lib = _lib.load()
+    o = _opts(leaf=leaf, blocking=blocking)
+    nbytes = lib.trinv_batched_workspace_bytes(m, batch, sizes_np.ctypes.data, ctypes.byref(o))
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    st = lib.trinv_tril_inverse_batched(m, batch, sizes_np.ctypes.data, n_dev.data_ptr(), off_np.ctypes.data,
+                                        off_dev.data_ptr(), L_packed.data_ptr(), X.data_ptr(), status.data_ptr(),
+                                        ctypes.byref(o), ws.data_ptr(), ws.numel(), _stream())
+    if st != _lib.OK and st != _lib.ERR_SINGULAR:
+        raise _lib.TrinvError(st, "trinv_tril_inverse_batched")
+    return X, status
+
+
+class TrilInverse(torch.autograd.Function):
+    """X = L^-1 with the hand-written adjoint gradL = -tril(X^T G X^T).
+
+    The forward's X is saved and reused by the backward (no recomputation)."""
+
+    @staticmethod
+    def forward(ctx, L, mode=None):
+        if L.dim() == 2:
+            X = tril_inverse(L, mode)
+        else:
+            X = batched_uniform_inverse(L, mode)
+        ctx.save_for_backward(X)
+        return X
+
+    @staticmethod
+    def backward(ctx, G):
+        (X,) = ctx.saved_tensors
+        return tril_inverse_backward(X, G), None
+
+
+def batched_uniform_inverse(L: torch.Tensor, mode=None) -> torch.Tensor:
+    """Inverse of a (batch, n, n) stack of lower-triangular matrices."""
+    _check_dev(L)
+    L = L.contiguous()
+    batch, n = L.shape[0], L.shape[-1]
+    sizes = [n] * batch
+    X, status = tril_inverse_batched(L.view(-1), sizes, mode=mode)
+    return X.view(batch, n, n)

@@ -1,0 +1,116 @@
+// Small HBM-bound helpers: flag initialisation and deterministic FP64
+// reductions (sums of squares for Frobenius norms).
+#include "common.h"
+#include "launch.h"
+
+namespace trinv {
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = (count + 255) / 256;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+// Block-wide sum of one double per thread (256 threads), fixed order.
+__device__ __forceinline__ double block_sum_256(double v) {
+  __shared__ double red[4];
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return r;
+}
+
+// One block per group of rows; partial[b] = sum of squares of its rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sumsq(const T* A, int64_t n, int64_t lda, int lower, int unit,
+                                               int64_t rows_per_block, double* partial) {
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = imin64(n, r0 + rows_per_block);
+  double s = 0.0;
+  for (int64_t i = r0; i < r1; ++i) {
+    const int64_t jmax = lower ? i + 1 : n;
+    for (int64_t j = threadIdx.x; j < jmax; j += 256) {
+      double v = (double)A[i * lda + j];
+      if (unit && j == i) v = 1.0;
+      s += v * v;
+    }
+  }
+  s = block_sum_256(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_sum(const double* partial, int64_t count, double* out) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) s += partial[i];
+  s = block_sum_256(s);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+hipError_t launch_reduce_sum(const double* partial, int64_t count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, partial, count, out);
+  return hipGetLastError();
+}
+
+__global__ void k_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    status[i] = first_bad[i] == ~0ull ? 0 : (int32_t)first_bad[i];
+}
+
+hipError_t launch_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = (count + 255) / 256;
+  hipLaunchKernelGGL(k_status_to_i32, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, first_bad,
+                     status, count);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sumsq(const T* A, int64_t n, int64_t lda, int lower, int unit, double* partial, int64_t npartial,
+                        double* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t rpb = (n + npartial - 1) / npartial;
+  const int64_t blocks = (n + rpb - 1) / rpb;
+  hipLaunchKernelGGL((k_sumsq<T>), dim3((unsigned)blocks), dim3(256), 0, s, A, n, lda, lower, unit, rpb, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_sum(partial, blocks, out, s);
+}
+template hipError_t launch_sumsq<double>(const double*, int64_t, int64_t, int, int, double*, int64_t, double*, hipStream_t);
+template hipError_t launch_sumsq<float>(const float*, int64_t, int64_t, int, int, double*, int64_t, double*, hipStream_t);
+
+// B = A^T through a 32 x 32 LDS tile (coalesced reads and writes).
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const T* A, int64_t lda, T* B, int64_t ldb, int64_t n) {
+  __shared__ T tile[32][33];
+  const int64_t bi = (int64_t)blockIdx.y * 32, bj = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi + r, j = bj + tx;
+    if (i < n && j < n) tile[r][tx] = A[i * lda + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bj + r, j = bi + tx;  // B(i, j) = A(j, i)
+    if (i < n && j < n) B[i * ldb + j] = tile[tx][r];
+  }
+}
+
+template <typename T>
+hipError_t launch_transpose(const T* A, int64_t lda, T* B, int64_t ldb, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned g = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL((k_transpose<T>), dim3(g, g), dim3(256), 0, s, A, lda, B, ldb, n);
+  return hipGetLastError();
+}
+template hipError_t launch_transpose<double>(const double*, int64_t, double*, int64_t, int64_t, hipStream_t);
+template hipError_t launch_transpose<float>(const float*, int64_t, float*, int64_t, int64_t, hipStream_t);
+
+}  // namespace trinv

@@ -1,0 +1,91 @@
+// Host-side launchers of the library's kernels (internal; not the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trinv {
+
+// ---------------------------------------------------------------- leaves
+// Inverts the diagonal leaf blocks of order `leaf` (the last one may be
+// shorter) of a strided batch of lower matrices. If Xlp is non-null a BF16
+// (lp_is_f16 = 0) or FP16 (1) copy of each leaf block is stored there too
+// (leading dimension ldxl, same batch stride). first_bad: atomic minimum of
+// the 1-based indices of exact zero pivots (init to all ones); one word for
+// the whole call, or one per matrix (per_matrix_status = 1).
+template <typename T>
+hipError_t launch_leaf(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int64_t stride, int64_t batch,
+                       int leaf, int unit, void* Xlp, int lp_is_f16, int64_t ldxl, uint64_t* first_bad,
+                       int per_matrix_status, hipStream_t s);
+
+// ---------------------------------------------------------------- tile products
+// A tile product D = alpha * op(A) * op(B) over a set of output tiles
+// (TM x TN = 128 x 128) with a K range per tile that skips the zero
+// triangles of triangular operands. The caller states the K range rule, the
+// tile set and the order in which tiles are dispatched (heaviest first).
+enum KLo { kLoZero = 0, kLoN0 = 1, kLoM0 = 2, kLoMax = 3 };   // k >= 0 | n0 | m0 | max(m0, n0)
+enum KHi { kHiK = 0, kHiM1 = 1, kHiN1 = 2 };                   // k < K | m0 + TM | n0 + TN
+enum Tiles { kAllTiles = 0, kLowerTiles = 1 };                  // all tiles | tiles with it >= jt
+enum Order {
+  kColAsc = 0,   // all tiles, tile column ascending (work shrinks with the column)
+  kRowDesc = 1,  // all tiles, tile row descending (work grows with the row)
+  kDiagDesc = 2, // lower tiles, it - jt descending
+  kRowAsc = 3,   // lower tiles, tile row ascending
+  kColDesc = 4   // lower tiles, tile column descending
+};
+// Element masks applied when an operand tile is staged (indices inside the
+// product): 0 none, 1 lower, 2 strict lower, 3 upper; for A(m, k) lower
+// means k <= m, for B(k, n) lower means k >= n.
+struct GemmBatch {
+  int64_t nmerge;                  // products per batch entry (merges of a level)
+  int64_t nbatch;                  // independent batch entries
+  int64_t M, N, K;                 // sizes of every product but the last merge
+  int64_t M_last, N_last, K_last;  // sizes of the last merge of each batch entry
+};
+
+// Element (i, j) of merge z of batch entry b is
+//   base[b * bstride2 + z * bstride + i * ld + j]   (or [.. + j * ld + i] if transposed).
+template <typename T>
+struct Operand {
+  T* base;
+  int64_t ld;
+  int64_t bstride;
+  int64_t bstride2;
+};
+
+template <typename TI>
+struct GemmArgs {
+  Operand<const TI> A, B;
+  Operand<TI> D;        // base null: D is not stored
+  Operand<TI> Zmirror;  // optional: zero the transposed position of each tile
+  Operand<void> Dlp;    // optional: BF16 (lp_is_f16 = 0) / FP16 (1) copy of D
+  int lp_is_f16;
+  double alpha;
+  int a_trans, b_trans;   // operand read transposed: A(m,k) = A[k*ld + m]
+  int amask, bmask;
+  int tiles, order, klo, khi;
+  int out_lower;          // store 0 where col > row
+  int mirror_skip_diag;   // do not zero the mirror of a diagonal tile
+  int subtract_identity;  // D = alpha*A*B - I (row == col inside the product)
+  double* tile_sq;        // optional: per-tile sum of squares of D (FP64)
+  GemmBatch bt;
+};
+
+template <typename TI, typename TC>
+hipError_t launch_gemm(const GemmArgs<TI>& a, hipStream_t s);
+int64_t gemm_tiles(const GemmBatch& bt, int tiles);
+
+// ---------------------------------------------------------------- elementwise
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t s);
+// out[0] = sum of squares of tril(A) (lower = 1) or A (lower = 0).
+template <typename T>
+hipError_t launch_sumsq(const T* A, int64_t n, int64_t lda, int lower, int unit, double* partial,
+                        int64_t npartial, double* out, hipStream_t s);
+hipError_t launch_reduce_sum(const double* partial, int64_t count, double* out, hipStream_t s);
+// status[i] = first_bad[i] == all ones ? 0 : first_bad[i]  (int32 per matrix).
+hipError_t launch_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count, hipStream_t s);
+// B = A^T for an n x n matrix.
+template <typename T>
+hipError_t launch_transpose(const T* A, int64_t lda, T* B, int64_t ldb, int64_t n, hipStream_t s);
+
+}  // namespace trinv
