@@ -194,6 +194,28 @@ size_t trinv_residual_workspace_bytes(int mode, int64_t n);
 int trinv_residual(int mode, int64_t n, const void *L, int64_t ldl, const void *X, int64_t ldx,
                    void *ws, size_t ws_bytes, trinv_stream_t stream, double *out_host);
 
+/*
+ * Measurement helpers (not part of the method). When profiling is enabled,
+ * every kernel launch of the library is bracketed by two HIP events recorded
+ * on the stream the launch uses, and filed under its kernel class with the
+ * launch's algorithmic flops and bytes (the work the method must do, not the
+ * work the tiles execute). trinv_profile_enable(1) starts a new profile
+ * (dropping the old one), trinv_profile_enable(0) stops recording.
+ * trinv_profile_read waits for the recorded events and writes up to
+ * max_entries per-class totals into out (host memory); it returns the number
+ * of classes, or a negative status on a HIP error.
+ */
+typedef struct {
+  char name[32];      /* kernel class */
+  int64_t launches;   /* launches recorded */
+  double total_ms;    /* summed event-to-event time of those launches */
+  double flops;       /* summed algorithmic flops */
+  double bytes;       /* summed algorithmic HBM bytes */
+} trinv_profile_entry;
+
+int trinv_profile_enable(int on);
+int trinv_profile_read(trinv_profile_entry *out, int max_entries);
+
 #ifdef __cplusplus
 }
 #endif

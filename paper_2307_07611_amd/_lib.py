@@ -21,8 +21,13 @@ EXPORTS = [
     "trinv_default_opts", "trinv_status_string", "trinv_workspace_bytes", "trinv_tril_inverse",
     "trinv_batched_workspace_bytes", "trinv_tril_inverse_batched", "trinv_backward_workspace_bytes",
     "trinv_tril_inverse_backward", "trinv_factored_workspace_bytes", "trinv_factored_inverse",
-    "trinv_residual_workspace_bytes", "trinv_residual",
+    "trinv_residual_workspace_bytes", "trinv_residual", "trinv_profile_enable", "trinv_profile_read",
 ]
+
+
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 class Opts(ctypes.Structure):
@@ -80,6 +85,10 @@ def load():
     lib.trinv_residual.argtypes = [ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp,
                                    ctypes.POINTER(ctypes.c_double)]
     lib.trinv_residual.restype = ctypes.c_int
+    lib.trinv_profile_enable.argtypes = [ctypes.c_int]
+    lib.trinv_profile_enable.restype = ctypes.c_int
+    lib.trinv_profile_read.argtypes = [ctypes.POINTER(ProfileEntry), ctypes.c_int]
+    lib.trinv_profile_read.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -200,3 +200,19 @@ def batched_uniform_inverse(L: torch.Tensor, mode=None) -> torch.Tensor:
     sizes = [n] * batch
     X, status = tril_inverse_batched(L.view(-1), sizes, mode=mode)
     return X.view(batch, n, n)
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start (dropping any previous one) or stop recording launch profiles."""
+    _lib.load().trinv_profile_enable(int(on))
+
+
+def profile_read() -> dict:
+    """Per kernel class: launches, total_ms, flops, bytes (waits for the GPU)."""
+    lib = _lib.load()
+    buf = (_lib.ProfileEntry * 64)()
+    n = lib.trinv_profile_read(buf, 64)
+    if n < 0:
+        raise _lib.TrinvError(-n, "trinv_profile_read")
+    return {buf[i].name.decode(): {"launches": buf[i].launches, "total_ms": buf[i].total_ms,
+                                   "flops": buf[i].flops, "bytes": buf[i].bytes} for i in range(min(n, 64))}

@@ -10,6 +10,7 @@
 // For n that is not leaf * 2^k the last leaf and the last block of each level
 // are shorter; every such split gives the same inverse in exact arithmetic.
 #include "api_internal.h"
+#include "profile.h"
 
 #include <algorithm>
 #include <cmath>
@@ -68,28 +69,43 @@ hipError_t run_levels(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int
     g1.A = {L + hA * ldl, ldl, st_l, stride};  // C = L21 of each merge
     g1.B = {X, ldx, st_x, stride};             // A^-1
     g1.D = {Tws, hA, hA * hA, tbatch};
-    g1.alpha = 1.0;
-    g1.bmask = 1;
+    g1.alpha = 1.0;  // A^-1 has exact zeros above its diagonal: no mask needed
     g1.tiles = kAllTiles;
     g1.order = kColAsc;
     g1.klo = kLoN0;
     g1.khi = kHiK;
     g1.bt = {lv.nmerge, batch, hA, hA, hA, lv.hB_last, hA, hA};
-    hipError_t e = launch_gemm<T, TC>(g1, s);
+    // Algorithmic work of a level: per merge hB*hA*(hA+1) flops for C*A^-1 and
+    // hA*hB*(hB+1) for B^-1*T; bytes: read C, A^-1, B^-1 (triangles), write X21.
+    const double es = sizeof(T);
+    const int64_t full = (lv.nmerge - 1) * batch;
+    const double hB = (double)lv.hB_last, fh = (double)hA;
+    const double fl1 = ((double)full * fh * fh * (fh + 1) + (double)batch * hB * fh * (fh + 1));
+    const double fl2 = ((double)full * fh * fh * (fh + 1) + (double)batch * fh * hB * (hB + 1));
+    const double by1 = es * ((double)full * (fh * fh + fh * fh / 2 + fh * fh) + (double)batch * (hB * fh + fh * fh / 2 + hB * fh));
+    const double by2 = es * ((double)full * (fh * fh / 2 + fh * fh + 2 * fh * fh) + (double)batch * (hB * hB / 2 + hB * fh + 2 * hB * fh));
+    const char* cls = sizeof(T) == 8 ? "gemm_f64" : "gemm_f32";
+    hipError_t e;
+    {
+      ProfLaunch pl(cls, fl1, by1, s);
+      e = launch_gemm<T, TC>(g1, s);
+    }
     if (e != hipSuccess) return e;
     GemmArgs<T> g2{};
     g2.A = {X + hA * ldx + hA, ldx, st_x, stride};  // B^-1
     g2.B = {Tws, hA, hA * hA, tbatch};
     g2.D = {X + hA * ldx, ldx, st_x, stride};       // X21
     g2.Zmirror = {X + hA, ldx, st_x, stride};       // X12 = 0
-    g2.alpha = -1.0;
-    g2.amask = 1;
+    g2.alpha = -1.0;  // B^-1 has exact zeros above its diagonal: no mask needed
     g2.tiles = kAllTiles;
     g2.order = kRowDesc;
     g2.klo = kLoZero;
     g2.khi = kHiM1;
     g2.bt = {lv.nmerge, batch, hA, hA, hA, lv.hB_last, hA, lv.hB_last};
-    e = launch_gemm<T, TC>(g2, s);
+    {
+      ProfLaunch pl(cls, fl2, by2, s);
+      e = launch_gemm<T, TC>(g2, s);
+    }
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -158,9 +174,12 @@ hipError_t plain_inverse(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, 
     Xout = (T*)w.Xt;
     ldout = n;
   }
-  if ((e = launch_leaf<T>(n, Lin, ldin, Xout, ldout, 0, 1, (int)leaf, o.unit_diag, nullptr, 0, 0, w.status, 0, s)) !=
-      hipSuccess)
-    return e;
+  {
+    const double nl = (double)((n + leaf - 1) / leaf), b = (double)leaf;
+    ProfLaunch pl(sizeof(T) == 8 ? "leaf_f64" : "leaf_f32", nl * b * b * b / 3.0, nl * b * b * sizeof(T), s);
+    e = launch_leaf<T>(n, Lin, ldin, Xout, ldout, 0, 1, (int)leaf, o.unit_diag, nullptr, 0, 0, w.status, 0, s);
+  }
+  if (e != hipSuccess) return e;
   if ((e = run_levels<T, T>(n, Lin, ldin, Xout, ldout, 0, 1, leaf, (T*)w.T, s)) != hipSuccess) return e;
   if (o.upper) return launch_transpose<T>(Xout, n, X, ldx, n, s);
   return hipSuccess;

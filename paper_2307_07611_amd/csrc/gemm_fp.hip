@@ -1,5 +1,5 @@
 // FP64 / FP32 MFMA tile products for the off-diagonal blocks of the
-// recursion and for the FP64 residual check.
+// recursion, the adjoint, the factored inverse and the FP64 residual check.
 //
 // The recursion (Section 4.1, algorithm COMBRIT with beta = 2, transposed to
 // the lower case) needs, for every merge of two inverted diagonal blocks A^-1
@@ -8,7 +8,7 @@
 //     X21 = -B^-1 * T      lower x full   (Ptf again)
 // Both are ordinary products whose K range per output tile is cut by the
 // triangle of the triangular operand, so MFMA work on the zero triangle is
-// limited to the diagonal K step. All merges of one level run in one launch.
+// limited to the diagonal K steps. All merges of one level run in one launch.
 //
 // Tiling for gfx950: a 256-thread workgroup computes a 128 x 128 tile of D
 // with 16 x 16 x 4 MFMAs (FP64: v_mfma_f64_16x16x4_f64, FP32:
@@ -18,6 +18,11 @@
 // multiplied. MFMA lane layouts (measured on gfx950): lane l supplies
 // A(l%16, l/16) and B(l/16, l%16); the FP64 result of register r is
 // D(4r + l/16, l%16), the FP32 one D(4(l/16) + r, l%16).
+//
+// Every option (transposed operands, element masks, K-range rule, tile set,
+// epilogue) is a template parameter, and out-of-range elements are handled by
+// loading a clamped in-range address and selecting zero, so the main loop has
+// no branches besides the loop itself.
 #include "common.h"
 #include "launch.h"
 
@@ -57,10 +62,11 @@ __device__ __forceinline__ int64_t tri_root(int64_t q) {
 }
 
 // Logical tile t -> (product z, tile row it, tile col jt) in the stated order.
-__device__ __forceinline__ void decode_tile(int64_t t, int tiles, int order, int64_t nz, int64_t tm,
-                                            int64_t tn, int64_t& z, int64_t& it, int64_t& jt) {
-  if (tiles == kAllTiles) {
-    if (order == kRowDesc) {  // tiles of one row (over all products) together
+template <int TILES, int ORDER>
+__device__ __forceinline__ void decode_tile(int64_t t, int64_t nz, int64_t tm, int64_t tn, int64_t& z, int64_t& it,
+                                            int64_t& jt) {
+  if (TILES == kAllTiles) {
+    if (ORDER == kRowDesc) {  // tiles of one row (over all products) together
       const int64_t g = t / (nz * tn), r = t % (nz * tn);
       it = tm - 1 - g;
       z = r / tn;
@@ -77,16 +83,31 @@ __device__ __forceinline__ void decode_tile(int64_t t, int tiles, int order, int
   z = t / per;
   const int64_t q = t % per;
   const int64_t u = tri_root(q), w = q - u * (u + 1) / 2;
-  if (order == kRowAsc) {
+  if (ORDER == kRowAsc) {
     it = u;
     jt = w;
-  } else if (order == kColDesc) {
+  } else if (ORDER == kColDesc) {
     jt = tm - 1 - u;
     it = jt + w;
   } else {  // kDiagDesc
     jt = w;
     it = w + (tm - 1 - u);
   }
+}
+
+template <int MASK, bool IS_A>
+__device__ __forceinline__ bool mask_ok(int64_t r, int64_t k) {
+  // A(r = m, k): lower k <= m, strict lower k < m, upper k >= m.
+  // B(k, r = n): lower k >= n, strict lower k > n, upper k <= n.
+  if (MASK == 0) return true;
+  if (IS_A) {
+    if (MASK == 1) return k <= r;
+    if (MASK == 2) return k < r;
+    return k >= r;
+  }
+  if (MASK == 1) return k >= r;
+  if (MASK == 2) return k > r;
+  return k <= r;
 }
 }  // namespace
 
@@ -97,7 +118,18 @@ int64_t gemm_tiles(const GemmBatch& bt, int tiles) {
   return nz * tm * tn;
 }
 
-template <typename TI, typename TC>
+// Epilogue flags.
+enum {
+  kEpStore = 1,
+  kEpMirror = 2,
+  kEpMirrorSkipDiag = 4,
+  kEpOutLower = 8,
+  kEpSubI = 16,
+  kEpTileSq = 32,
+  kEpLowp = 64
+};
+
+template <typename TI, typename TC, int AT, int BT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EP>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs<TI> a) {
   typedef Mma<TC> MM;
   __shared__ TC lds[2 * (ABUF + BBUF)];
@@ -105,72 +137,114 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<TI> a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  const GemmBatch& bt = a.bt;
+  const GemmBatch bt = a.bt;
   const int64_t tm = (bt.M + TM - 1) / TM, tn = (bt.N + TN - 1) / TN;
   const int64_t nz = bt.nmerge * bt.nbatch;
-  const int64_t total = (a.tiles == kLowerTiles) ? nz * tm * (tm + 1) / 2 : nz * tm * tn;
+  const int64_t total = (TILES == kLowerTiles) ? nz * tm * (tm + 1) / 2 : nz * tm * tn;
   const int64_t t = xcd_remap(blockIdx.x, total, 8);
   int64_t z, it, jt;
-  decode_tile(t, a.tiles, a.order, nz, tm, tn, z, it, jt);
+  decode_tile<TILES, ORDER>(t, nz, tm, tn, z, it, jt);
   const int64_t zb = z / bt.nmerge, zk = z % bt.nmerge;
   const bool last = (zk == bt.nmerge - 1);
   const int64_t M = last ? bt.M_last : bt.M, N = last ? bt.N_last : bt.N, K = last ? bt.K_last : bt.K;
   const int64_t m0 = it * TM, n0 = jt * TN;
   if (m0 >= M || n0 >= N) {
-    if (a.tile_sq && tid == 0) a.tile_sq[t] = 0.0;
+    if ((EP & kEpTileSq) && tid == 0) a.tile_sq[t] = 0.0;
     return;
   }
 
   int64_t klo = 0, khi = K;
-  if (a.klo == kLoN0) klo = n0;
-  else if (a.klo == kLoM0) klo = m0;
-  else if (a.klo == kLoMax) klo = imax64(m0, n0);
-  if (a.khi == kHiM1) khi = imin64(K, m0 + TM);
-  else if (a.khi == kHiN1) khi = imin64(K, n0 + TN);
+  if (KLO == kLoN0) klo = n0;
+  if (KLO == kLoM0) klo = m0;
+  if (KLO == kLoMax) klo = imax64(m0, n0);
+  if (KHI == kHiM1) khi = imin64(K, m0 + TM);
+  if (KHI == kHiN1) khi = imin64(K, n0 + TN);
   klo = (klo / KT) * KT;
 
   const TI* __restrict__ Ab = a.A.base + zb * a.A.bstride2 + zk * a.A.bstride;
   const TI* __restrict__ Bb = a.B.base + zb * a.B.bstride2 + zk * a.B.bstride;
-  const int64_t a_sm = a.a_trans ? 1 : a.A.ld, a_sk = a.a_trans ? a.A.ld : 1;
-  const int64_t b_sk = a.b_trans ? 1 : a.B.ld, b_sn = a.b_trans ? a.B.ld : 1;
+  const int64_t lda = a.A.ld, ldb = a.B.ld;
 
   // Staging maps (8 elements of each operand tile per thread), chosen so that
   // consecutive lanes read consecutive addresses:
   //   A 128 x 16: row-major -> 16 lanes along k; transposed -> 128 lanes along m.
   //   B 16 x 128: row-major -> 128 lanes along n; transposed -> 16 lanes along k.
-  const int am = a.a_trans ? (tid & 127) : (tid >> 4), ak = a.a_trans ? (tid >> 7) : (tid & 15);
-  const int am_step = a.a_trans ? 0 : 16, ak_step = a.a_trans ? 2 : 0;
-  const int bn = a.b_trans ? (tid >> 4) : (tid & 127), bk = a.b_trans ? (tid & 15) : (tid >> 7);
-  const int bn_step = a.b_trans ? 16 : 0, bk_step = a.b_trans ? 0 : 2;
-  TC ra[8], rb[8];
+  constexpr int AM_STEP = AT ? 0 : 16, AK_STEP = AT ? 2 : 0;
+  constexpr int BN_STEP = BT ? 16 : 0, BK_STEP = BT ? 0 : 2;
+  const int am = AT ? (tid & 127) : (tid >> 4), ak = AT ? (tid >> 7) : (tid & 15);
+  const int bn = BT ? (tid >> 4) : (tid & 127), bk = BT ? (tid & 15) : (tid >> 7);
 
-  auto load = [&](int64_t k0) {
+  // Each staged element has a fixed "row" index for the whole tile (m for A,
+  // n for B). Rows beyond M (columns beyond N) only feed outputs that are not
+  // stored, so they are clamped to the last valid row and loaded as is; only
+  // the K direction needs zero fill (k >= K) and the element masks, and only
+  // K steps that reach the K edge or a masked diagonal take that guarded path.
+  // Each thread keeps one pointer per staged element and advances it by one
+  // K step per iteration.
+  const TI* pa[8];
+  const TI* pb[8];
+  const int64_t a_kstep = AT ? (int64_t)KT * lda : (int64_t)KT;  // pointer advance per K step
+  const int64_t b_kstep = BT ? (int64_t)KT : (int64_t)KT * ldb;
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int64_t m = imin64(m0 + am + AM_STEP * p, M - 1);
+    const int64_t ka = klo + ak + AK_STEP * p;
+    pa[p] = AT ? Ab + ka * lda + m : Ab + m * lda + ka;
+    const int64_t nn = imin64(n0 + bn + BN_STEP * p, N - 1);
+    const int64_t kb = klo + bk + BK_STEP * p;
+    pb[p] = BT ? Bb + nn * ldb + kb : Bb + kb * ldb + nn;
+  }
+
+  TC ra[8], rb[8];
+  // Fast path: K step fully inside [0, K) and away from masked diagonals.
+  auto load_fast = [&]() {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) ra[p] = (TC)*pa[p];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) rb[p] = (TC)*pb[p];
+  };
+  // Guarded path: zero fill beyond K and element masks. The address is
+  // clamped back inside the operand before the load.
+  auto load_guard = [&](int64_t k0) {
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int64_t m = m0 + am + am_step * p, k = k0 + ak + ak_step * p;
-      bool ok = (m < M) && (k < K);
-      if (a.amask == 1) ok = ok && (k <= m);
-      else if (a.amask == 2) ok = ok && (k < m);
-      else if (a.amask == 3) ok = ok && (k >= m);
-      ra[p] = ok ? (TC)Ab[m * a_sm + k * a_sk] : (TC)0;
+      const int64_t k = k0 + ak + AK_STEP * p;
+      const bool ok = (k < K) && mask_ok<AM, true>(m0 + am + AM_STEP * p, k);
+      const int64_t back = k < K ? 0 : (k - (K - 1));  // elements of K to step back
+      const TI v = *(pa[p] - (AT ? back * lda : back));
+      ra[p] = ok ? (TC)v : (TC)0;
     }
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int64_t k = k0 + bk + bk_step * p, nn = n0 + bn + bn_step * p;
-      bool ok = (k < K) && (nn < N);
-      if (a.bmask == 1) ok = ok && (k >= nn);
-      else if (a.bmask == 2) ok = ok && (k > nn);
-      else if (a.bmask == 3) ok = ok && (k <= nn);
-      rb[p] = ok ? (TC)Bb[k * b_sk + nn * b_sn] : (TC)0;
+      const int64_t k = k0 + bk + BK_STEP * p;
+      const bool ok = (k < K) && mask_ok<BM, false>(n0 + bn + BN_STEP * p, k);
+      const int64_t back = k < K ? 0 : (k - (K - 1));
+      const TI v = *(pb[p] - (BT ? back : back * ldb));
+      rb[p] = ok ? (TC)v : (TC)0;
+    }
+  };
+  auto needs_guard = [&](int64_t k0) -> bool {
+    if (k0 + KT > K) return true;
+    if (AM != 0 && k0 + KT > m0 && k0 < m0 + TM) return true;
+    if (BM != 0 && k0 + KT > n0 && k0 < n0 + TN) return true;
+    return false;
+  };
+  auto load = [&](int64_t k0) {
+    if (needs_guard(k0)) load_guard(k0);
+    else load_fast();
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      pa[p] += a_kstep;
+      pb[p] += b_kstep;
     }
   };
   auto store = [&](int buf) {
     TC* As = lds + buf * (ABUF + BBUF);
     TC* Bs = As + ABUF;
 #pragma unroll
-    for (int p = 0; p < 8; ++p) As[(am + am_step * p) * SA + ak + ak_step * p] = ra[p];
+    for (int p = 0; p < 8; ++p) As[(am + AM_STEP * p) * SA + ak + AK_STEP * p] = ra[p];
 #pragma unroll
-    for (int p = 0; p < 8; ++p) Bs[(bk + bk_step * p) * SB + bn + bn_step * p] = rb[p];
+    for (int p = 0; p < 8; ++p) Bs[(bk + BK_STEP * p) * SB + bn + BN_STEP * p] = rb[p];
   };
 
   typename MM::acc_t acc[4][4];
@@ -210,9 +284,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<TI> a) {
   }
 
   // Epilogue: scale, identity subtraction, lower-only output, stores, norm.
-  TI* __restrict__ Db = a.D.base ? a.D.base + zb * a.D.bstride2 + zk * a.D.bstride : nullptr;
-  char* __restrict__ Lb =
-      a.Dlp.base ? (char*)a.Dlp.base + 2 * (zb * a.Dlp.bstride2 + zk * a.Dlp.bstride) : nullptr;
+  TI* __restrict__ Db = (EP & kEpStore) ? a.D.base + zb * a.D.bstride2 + zk * a.D.bstride : nullptr;
+  char* __restrict__ Lb = (EP & kEpLowp) ? (char*)a.Dlp.base + 2 * (zb * a.Dlp.bstride2 + zk * a.Dlp.bstride) : nullptr;
+  const double alpha = a.alpha;
+  const bool full_tile = (m0 + TM <= M) && (n0 + TN <= N);
   double sq = 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -222,13 +297,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<TI> a) {
       for (int r = 0; r < 4; ++r) {
         const int64_t row = m0 + wm * 64 + i * 16 + MM::row(lane, r);
         const int64_t col = n0 + wn * 64 + j * 16 + (lane & 15);
-        if (row < M && col < N) {
-          double v = a.alpha * (double)acc[i][j][r];
-          if (a.subtract_identity && row == col) v -= 1.0;
-          if (a.out_lower && col > row) v = 0.0;
-          if (Db) Db[row * a.D.ld + col] = (TI)v;
-          sq += v * v;
-          if (Lb) {
+        if (full_tile || (row < M && col < N)) {
+          double v = alpha * (double)acc[i][j][r];
+          if ((EP & kEpSubI) && row == col) v -= 1.0;
+          if ((EP & kEpOutLower) && col > row) v = 0.0;
+          if (EP & kEpStore) Db[row * a.D.ld + col] = (TI)v;
+          if (EP & kEpTileSq) sq += v * v;
+          if (EP & kEpLowp) {
             const int64_t e = row * a.Dlp.ld + col;
             if (a.lp_is_f16) ((_Float16*)Lb)[e] = (_Float16)(float)v;
             else ((__bf16*)Lb)[e] = (__bf16)(float)v;
@@ -236,7 +311,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<TI> a) {
         }
       }
 
-  if (a.Zmirror.base && !(a.mirror_skip_diag && it == jt)) {
+  if ((EP & kEpMirror) && !((EP & kEpMirrorSkipDiag) && it == jt)) {
     TI* Zb = a.Zmirror.base + zb * a.Zmirror.bstride2 + zk * a.Zmirror.bstride;
     for (int e = tid; e < TM * TN; e += 256) {
       const int64_t mr = n0 + e / TM, mc = m0 + e % TM;
@@ -244,12 +319,33 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<TI> a) {
     }
   }
 
-  if (a.tile_sq) {
+  if (EP & kEpTileSq) {
     for (int m = 32; m >= 1; m >>= 1) sq += __shfl_xor(sq, m, 64);
     if (lane == 0) red[wave] = sq;
     __syncthreads();
     if (tid == 0) a.tile_sq[t] = (red[0] + red[1]) + (red[2] + red[3]);
   }
+}
+
+// Runtime options -> one of the instantiated configurations.
+template <typename TI, typename TC, int AT, int BT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EP>
+static hipError_t go(const GemmArgs<TI>& a, hipStream_t s, int64_t total) {
+  hipLaunchKernelGGL((k_gemm<TI, TC, AT, BT, AM, BM, TILES, ORDER, KLO, KHI, EP>), dim3((unsigned)total), dim3(256), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
+template <typename TI>
+static int epilogue_of(const GemmArgs<TI>& a) {
+  int ep = 0;
+  if (a.D.base) ep |= kEpStore;
+  if (a.Zmirror.base) ep |= kEpMirror;
+  if (a.mirror_skip_diag) ep |= kEpMirrorSkipDiag;
+  if (a.out_lower) ep |= kEpOutLower;
+  if (a.subtract_identity) ep |= kEpSubI;
+  if (a.tile_sq) ep |= kEpTileSq;
+  if (a.Dlp.base) ep |= kEpLowp;
+  return ep;
 }
 
 template <typename TI, typename TC>
@@ -258,8 +354,41 @@ hipError_t launch_gemm(const GemmArgs<TI>& a, hipStream_t s) {
   if (total <= 0) return hipSuccess;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
   if (a.tiles == kLowerTiles && a.bt.M != a.bt.N) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_gemm<TI, TC>), dim3((unsigned)total), dim3(256), 0, s, a);
-  return hipGetLastError();
+  const int ep = epilogue_of(a);
+  // Configurations used by the library (see the callers):
+  // level product C * A^-1
+  if (!a.a_trans && !a.b_trans && a.amask == 0 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kColAsc &&
+      a.klo == kLoN0 && a.khi == kHiK) {
+    if (ep == kEpStore) return go<TI, TC, 0, 0, 0, 0, kAllTiles, kColAsc, kLoN0, kHiK, kEpStore>(a, s, total);
+    if (ep == (kEpStore | kEpLowp))
+      return go<TI, TC, 0, 0, 0, 0, kAllTiles, kColAsc, kLoN0, kHiK, kEpStore | kEpLowp>(a, s, total);
+  }
+  // level product -B^-1 * T, zeroing the mirrored block
+  if (!a.a_trans && !a.b_trans && a.amask == 0 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kRowDesc &&
+      a.klo == kLoZero && a.khi == kHiM1) {
+    if (ep == (kEpStore | kEpMirror))
+      return go<TI, TC, 0, 0, 0, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kEpStore | kEpMirror>(a, s, total);
+    if (ep == (kEpStore | kEpMirror | kEpLowp))
+      return go<TI, TC, 0, 0, 0, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kEpStore | kEpMirror | kEpLowp>(a, s, total);
+  }
+  // residual check: tril(L) * X - I, norm only
+  if (!a.a_trans && !a.b_trans && a.amask == 1 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kRowDesc &&
+      a.klo == kLoZero && a.khi == kHiM1 && ep == (kEpSubI | kEpTileSq))
+    return go<TI, TC, 0, 0, 1, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kEpSubI | kEpTileSq>(a, s, total);
+  // factored: Uinv * Linv
+  if (!a.a_trans && !a.b_trans && a.amask == 3 && a.bmask == 1 && a.tiles == kAllTiles && a.order == kColAsc &&
+      a.klo == kLoMax && a.khi == kHiK && ep == kEpStore)
+    return go<TI, TC, 0, 0, 3, 1, kAllTiles, kColAsc, kLoMax, kHiK, kEpStore>(a, s, total);
+  // adjoint: M = tril(X^T tril(G))
+  if (a.a_trans && !a.b_trans && a.amask == 3 && a.bmask == 1 && a.tiles == kLowerTiles && a.order == kRowAsc &&
+      a.klo == kLoM0 && a.khi == kHiK && ep == (kEpStore | kEpOutLower))
+    return go<TI, TC, 1, 0, 3, 1, kLowerTiles, kRowAsc, kLoM0, kHiK, kEpStore | kEpOutLower>(a, s, total);
+  // adjoint: grad = -tril(M X^T), zeroing the strict upper tiles
+  if (!a.a_trans && a.b_trans && a.amask == 1 && a.bmask == 3 && a.tiles == kLowerTiles && a.order == kColDesc &&
+      a.klo == kLoZero && a.khi == kHiN1 && ep == (kEpStore | kEpOutLower | kEpMirror | kEpMirrorSkipDiag))
+    return go<TI, TC, 0, 1, 1, 3, kLowerTiles, kColDesc, kLoZero, kHiN1,
+              kEpStore | kEpOutLower | kEpMirror | kEpMirrorSkipDiag>(a, s, total);
+  return hipErrorInvalidValue;
 }
 
 template hipError_t launch_gemm<double, double>(const GemmArgs<double>&, hipStream_t);

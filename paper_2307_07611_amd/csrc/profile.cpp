@@ -1,0 +1,103 @@
+// Launch profiling (measurement helper): when enabled, every kernel launch of
+// the library is bracketed by a pair of HIP events recorded on the launch's
+// own stream, together with the launch's algorithmic flops and bytes. The
+// pairs are resolved (and the GPU waited for) only when the profile is read.
+#include "profile.h"
+
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace trinv {
+
+namespace {
+struct Rec {
+  std::string cls;
+  double flops, bytes;
+  hipEvent_t a, b;
+};
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t get_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+bool profiling_on() { return g_on; }
+
+ProfLaunch::ProfLaunch(const char* cls, double flops, double bytes, hipStream_t s) : s_(s) {
+  if (!g_on) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Rec r;
+  r.cls = cls;
+  r.flops = flops;
+  r.bytes = bytes;
+  r.a = get_event();
+  r.b = get_event();
+  if (!r.a || !r.b) return;
+  if (hipEventRecord(r.a, s) != hipSuccess) return;
+  g_recs.push_back(r);
+  idx_ = (long)g_recs.size() - 1;
+}
+
+ProfLaunch::~ProfLaunch() {
+  if (idx_ < 0) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (idx_ < (long)g_recs.size()) (void)hipEventRecord(g_recs[idx_].b, s_);
+}
+
+}  // namespace trinv
+
+using namespace trinv;
+
+extern "C" int trinv_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_on = on != 0;
+  for (Rec& r : g_recs) {
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  return TRINV_OK;
+}
+
+extern "C" int trinv_profile_read(trinv_profile_entry* out, int max_entries) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::map<std::string, trinv_profile_entry> agg;
+  std::vector<std::string> order;
+  for (Rec& r : g_recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return -TRINV_ERR_HIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return -TRINV_ERR_HIP;
+    auto it = agg.find(r.cls);
+    if (it == agg.end()) {
+      trinv_profile_entry e;
+      std::memset(&e, 0, sizeof(e));
+      std::strncpy(e.name, r.cls.c_str(), sizeof(e.name) - 1);
+      it = agg.emplace(r.cls, e).first;
+      order.push_back(r.cls);
+    }
+    it->second.launches += 1;
+    it->second.total_ms += ms;
+    it->second.flops += r.flops;
+    it->second.bytes += r.bytes;
+  }
+  int n = 0;
+  for (const std::string& k : order) {
+    if (n < max_entries && out) out[n] = agg[k];
+    ++n;
+  }
+  return n;
+}
