@@ -54,6 +54,18 @@ __global__ __launch_bounds__(256) void k_reduce_sum(const double* partial, int64
   if (threadIdx.x == 0) out[0] = s;
 }
 
+__global__ __launch_bounds__(256) void k_sumsq_vec(const double* v, int64_t count, double* out) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) s += v[i] * v[i];
+  s = block_sum_256(s);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+hipError_t launch_sumsq_vec(const double* v, int64_t count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sumsq_vec, dim3(1), dim3(256), 0, s, v, count, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_sum(const double* partial, int64_t count, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, partial, count, out);
   return hipGetLastError();

@@ -126,7 +126,8 @@ enum {
   kEpOutLower = 8,
   kEpSubI = 16,
   kEpTileSq = 32,
-  kEpLowp = 64
+  kEpLowp = 64,
+  kEpRefineResid = 128
 };
 
 template <typename TI, typename TC, int AT, int BT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EP>
@@ -149,7 +150,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<TI> a) {
   const int64_t M = last ? bt.M_last : bt.M, N = last ? bt.N_last : bt.N, K = last ? bt.K_last : bt.K;
   const int64_t m0 = it * TM, n0 = jt * TN;
   if (m0 >= M || n0 >= N) {
-    if ((EP & kEpTileSq) && tid == 0) a.tile_sq[t] = 0.0;
+    if ((EP & (kEpTileSq | kEpRefineResid)) && tid == 0) a.tile_sq[t] = 0.0;
+    if ((EP & kEpRefineResid) && tid == 0) a.tile_sqx[t] = 0.0;
     return;
   }
 
@@ -283,6 +285,52 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<TI> a) {
     }
   }
 
+  if (EP & kEpRefineResid) {
+    // R = I - L X from acc = (N_L N_X)(row, col) and the O(n^2) FP64 terms.
+    double sq = 0.0, sqx = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + wm * 64 + i * 16 + MM::row(lane, r);
+          const int64_t col = n0 + wn * 64 + j * 16 + (lane & 15);
+          if (row < M && col < N && col <= row) {
+            const double lii = a.dL[row];
+            const double xij = (double)a.Xfull[row * a.ldx + col];
+            double rv;
+            if (row == col) rv = fma(-lii, xij, 1.0);
+            else rv = -(double)acc[i][j][r] - lii * xij - (double)a.Lfull[row * a.ldl + col] * a.dX[col];
+            a.R32[row * a.ldr + col] = (float)rv;
+            const int64_t e = col * a.ldrt + row;
+            if (a.lp_is_f16) ((_Float16*)a.Rt)[e] = (_Float16)(float)rv;
+            else ((__bf16*)a.Rt)[e] = (__bf16)(float)rv;
+            sq += rv * rv;
+            sqx += xij * xij;
+          } else if (row < M && col < N) {  // above the diagonal: zero in the transposed copy
+            const int64_t e = col * a.ldrt + row;
+            if (a.lp_is_f16) ((_Float16*)a.Rt)[e] = (_Float16)0.f;
+            else ((__bf16*)a.Rt)[e] = (__bf16)0.f;
+          }
+        }
+    for (int m = 32; m >= 1; m >>= 1) {
+      sq += __shfl_xor(sq, m, 64);
+      sqx += __shfl_xor(sqx, m, 64);
+    }
+    __shared__ double red2[2][4];
+    if (lane == 0) {
+      red2[0][wave] = sq;
+      red2[1][wave] = sqx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      a.tile_sq[t] = (red2[0][0] + red2[0][1]) + (red2[0][2] + red2[0][3]);
+      a.tile_sqx[t] = (red2[1][0] + red2[1][1]) + (red2[1][2] + red2[1][3]);
+    }
+    return;
+  }
+
   // Epilogue: scale, identity subtraction, lower-only output, stores, norm.
   TI* __restrict__ Db = (EP & kEpStore) ? a.D.base + zb * a.D.bstride2 + zk * a.D.bstride : nullptr;
   char* __restrict__ Lb = (EP & kEpLowp) ? (char*)a.Dlp.base + 2 * (zb * a.Dlp.bstride2 + zk * a.Dlp.bstride) : nullptr;
@@ -345,6 +393,7 @@ static int epilogue_of(const GemmArgs<TI>& a) {
   if (a.subtract_identity) ep |= kEpSubI;
   if (a.tile_sq) ep |= kEpTileSq;
   if (a.Dlp.base) ep |= kEpLowp;
+  if (a.refine_resid) ep = kEpRefineResid;
   return ep;
 }
 
@@ -388,6 +437,10 @@ hipError_t launch_gemm(const GemmArgs<TI>& a, hipStream_t s) {
       a.klo == kLoZero && a.khi == kHiN1 && ep == (kEpStore | kEpOutLower | kEpMirror | kEpMirrorSkipDiag))
     return go<TI, TC, 0, 1, 1, 3, kLowerTiles, kColDesc, kLoZero, kHiN1,
               kEpStore | kEpOutLower | kEpMirror | kEpMirrorSkipDiag>(a, s, total);
+  // refinement residual on FP64 MFMA: N_L N_X (both strictly lower), lower tiles
+  if (!a.a_trans && !a.b_trans && a.amask == 2 && a.bmask == 2 && a.tiles == kLowerTiles && a.order == kDiagDesc &&
+      a.klo == kLoN0 && a.khi == kHiM1 && ep == kEpRefineResid)
+    return go<TI, TC, 0, 0, 2, 2, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kEpRefineResid>(a, s, total);
   return hipErrorInvalidValue;
 }
 

@@ -1,0 +1,446 @@
+// Low-precision MFMA tile products (BF16 or FP16 inputs, FP32 accumulation)
+// for the mixed-precision path: the off-diagonal products of the recursion
+// (Section 4.1, algorithm COMBRIT with beta = 2) and the products of the
+// Newton-Schulz refinement (not in the paper).
+//
+// Tiling for gfx950: a 256-thread workgroup computes a 256 x 256 tile with
+// v_mfma_f32_32x32x16_{bf16,f16}; each wave owns a 128 x 128 sub-tile
+// (4 x 4 blocks of 32 x 32, 256 FP32 accumulators per lane). Both operands
+// are k-contiguous in memory (B is stored transposed), so a K step is staged
+// with 16-byte loads into two LDS buffers and every MFMA operand is one
+// 16-byte LDS read. Lane layouts (measured on gfx950): lane l supplies
+// A(l%32, 8(l/32)+e) and B(8(l/32)+e, l%32), e = 0..7, and receives
+// D(8(r/4) + 4(l/32) + r%4, l%32) in register r.
+//
+// The optional 3-product split forms A_hi B_hi + A_hi B_lo + A_lo B_hi in the
+// same accumulator (an operand v is carried as hi = round(v) plus
+// lo = round(v - hi), which multiplies the precision by the slice width).
+// Rows beyond M (columns beyond N) are clamped to the last valid one: they
+// only feed outputs that are not stored. Zero fill beyond K and the element
+// masks of triangular operands are applied only in K steps that reach the K
+// edge or a masked diagonal.
+#include <type_traits>
+
+#include "common.h"
+#include "lowp.h"
+
+namespace trinv {
+
+// Calls f(integral_constant<int, B>), ..., f(integral_constant<int, E-1>): the
+// index is a compile-time constant in every call, so register arrays indexed
+// by it never need memory.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+namespace {
+constexpr int LT = 256;  // workgroup tile (rows and columns)
+
+template <int NSPLIT>
+struct LpShape {
+  static constexpr int KT = NSPLIT == 1 ? 32 : 16;  // K per LDS stage
+  static constexpr int SK = KT + 8;                 // LDS row stride (elements)
+  static constexpr int TILE = LT * SK;              // elements of one staged operand tile
+  static constexpr int NT = NSPLIT == 1 ? 2 : 4;    // staged tiles per stage
+  static constexpr int CHUNKS = LT * KT / 8;        // 16-byte chunks per tile
+  static constexpr int CPT = CHUNKS / 256;          // chunks per thread per tile
+  static constexpr int CPR = KT / 8;                // chunks per row
+};
+
+typedef unsigned short u16;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int F16>
+__device__ __forceinline__ f32x16 mma(u32x4 a, u32x4 b, f32x16 c) {
+  if (F16) return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+template <int F16>
+__device__ __forceinline__ u16 to_lp(float v) {
+  if (F16) return __builtin_bit_cast(u16, (_Float16)v);
+  return __builtin_bit_cast(u16, (__bf16)v);
+}
+
+__device__ __forceinline__ int64_t tri_root_lp(int64_t q) {
+  int64_t u = (int64_t)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+  while (u * (u + 1) / 2 > q) --u;
+  while ((u + 1) * (u + 2) / 2 <= q) ++u;
+  return u;
+}
+
+template <int TILES, int ORDER>
+__device__ __forceinline__ void decode_lp(int64_t t, int64_t nz, int64_t tm, int64_t tn, int64_t& z, int64_t& it,
+                                          int64_t& jt) {
+  if (TILES == kAllTiles) {
+    if (ORDER == kRowDesc) {
+      const int64_t g = t / (nz * tn), r = t % (nz * tn);
+      it = tm - 1 - g;
+      z = r / tn;
+      jt = r % tn;
+    } else {
+      const int64_t g = t / (nz * tm), r = t % (nz * tm);
+      jt = g;
+      z = r / tm;
+      it = r % tm;
+    }
+    return;
+  }
+  const int64_t per = tm * (tm + 1) / 2;
+  z = t / per;
+  const int64_t q = t % per;
+  const int64_t u = tri_root_lp(q), w = q - u * (u + 1) / 2;
+  jt = w;  // kDiagDesc: offset it - jt descending
+  it = w + (tm - 1 - u);
+}
+
+// Element masks (A(m,k): 1 lower k<=m, 2 strict k<m; B(k,n): 1 lower k>=n, 2 strict k>n).
+template <int MASK, bool IS_A>
+__device__ __forceinline__ bool lp_mask_ok(int64_t r, int64_t k) {
+  if (MASK == 0) return true;
+  if (IS_A) return MASK == 1 ? (k <= r) : (k < r);
+  return MASK == 1 ? (k >= r) : (k > r);
+}
+}  // namespace
+
+int64_t gemm_lp_tiles(const GemmBatch& bt, int tiles) {
+  const int64_t tm = (bt.M + LT - 1) / LT, tn = (bt.N + LT - 1) / LT;
+  if (tiles == kLowerTiles) return bt.nmerge * tm * (tm + 1) / 2;
+  return bt.nmerge * tm * tn;
+}
+
+template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
+  typedef LpShape<NSPLIT> S;
+  constexpr int KT = S::KT, SK = S::SK;
+  extern __shared__ __attribute__((aligned(16))) u16 lds[];  // 2 stages x NT tiles x TILE elements
+  __shared__ double red[2][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const GemmBatch bt = a.bt;
+  const int64_t tm = (bt.M + LT - 1) / LT, tn = (bt.N + LT - 1) / LT;
+  const int64_t nz = bt.nmerge;
+  const int64_t total = (TILES == kLowerTiles) ? nz * tm * (tm + 1) / 2 : nz * tm * tn;
+  const int64_t t = xcd_remap(blockIdx.x, total, 4);
+  int64_t z, it, jt;
+  decode_lp<TILES, ORDER>(t, nz, tm, tn, z, it, jt);
+  const bool last = (z == bt.nmerge - 1);
+  const int64_t M = last ? bt.M_last : bt.M, N = last ? bt.N_last : bt.N, K = last ? bt.K_last : bt.K;
+  const int64_t m0 = it * LT, n0 = jt * LT;
+  if (m0 >= M || n0 >= N) {
+    if (EPI == kLpEpResid && tid == 0) {
+      a.tile_sq[t] = 0.0;
+      a.tile_sqx[t] = 0.0;
+    }
+    return;
+  }
+  int64_t klo = 0, khi = K;
+  if (KLO == kLoN0) klo = n0;
+  if (KHI == kHiM1) khi = imin64(K, m0 + LT);
+  klo = (klo / KT) * KT;
+
+  // Staging: chunk c = tid + 256 p of a 256 x KT tile -> row c / CPR, k offset 8 (c % CPR).
+  const u16* pa[NSPLIT == 1 ? 1 : 2][S::CPT];
+  const u16* pb[NSPLIT == 1 ? 1 : 2][S::CPT];
+  int rowl[S::CPT], kq[S::CPT];
+  const u16* Ahi = (const u16*)a.A_hi + z * a.a_bstride;
+  const u16* Bhi = (const u16*)a.Bt_hi + z * a.b_bstride;
+  const u16* Alo = NSPLIT == 3 ? (const u16*)a.A_lo + z * a.a_bstride : nullptr;
+  const u16* Blo = NSPLIT == 3 ? (const u16*)a.Bt_lo + z * a.b_bstride : nullptr;
+#pragma unroll
+  for (int p = 0; p < S::CPT; ++p) {
+    const int c = tid + 256 * p;
+    rowl[p] = c / S::CPR;
+    kq[p] = 8 * (c % S::CPR);
+    const int64_t ma = imin64(m0 + rowl[p], M - 1), nb = imin64(n0 + rowl[p], N - 1);
+    pa[0][p] = Ahi + ma * a.lda + klo + kq[p];
+    pb[0][p] = Bhi + nb * a.ldb + klo + kq[p];
+    if (NSPLIT == 3) {
+      pa[NSPLIT == 1 ? 0 : 1][p] = Alo + ma * a.lda + klo + kq[p];
+      pb[NSPLIT == 1 ? 0 : 1][p] = Blo + nb * a.ldb + klo + kq[p];
+    }
+  }
+  constexpr int NS = NSPLIT == 1 ? 1 : 2;
+  u32x4 ra[NS][S::CPT], rb[NS][S::CPT];
+
+  auto load = [&](int64_t k0) {
+    bool guard = (k0 + KT > K);
+    if (AM != 0 && k0 + KT > m0 && k0 < m0 + LT) guard = true;
+    if (BM != 0 && k0 + KT > n0 && k0 < n0 + LT) guard = true;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int p = 0; p < S::CPT; ++p) {
+        ra[s][p] = *(const u32x4*)pa[s][p];
+        rb[s][p] = *(const u32x4*)pb[s][p];
+      }
+    if (guard) {
+#pragma unroll
+      for (int p = 0; p < S::CPT; ++p) {
+        const int64_t kb = k0 + kq[p];
+        const int64_t ma = m0 + rowl[p], nb = n0 + rowl[p];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int64_t k = kb + e;
+          const bool oka = (k < K) && lp_mask_ok<AM, true>(ma, k);
+          const bool okb = (k < K) && lp_mask_ok<BM, false>(nb, k);
+          const unsigned sh = 16 * (e & 1);
+          const unsigned keep_a = oka ? 0xffffu << sh : 0u, keep_b = okb ? 0xffffu << sh : 0u;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            ra[s][p][e >> 1] &= (keep_a | ~(0xffffu << sh));
+            rb[s][p][e >> 1] &= (keep_b | ~(0xffffu << sh));
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int p = 0; p < S::CPT; ++p) {
+        pa[s][p] += KT;
+        pb[s][p] += KT;
+      }
+  };
+  auto store = [&](int buf) {
+    u16* base = lds + buf * (S::NT * S::TILE);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int p = 0; p < S::CPT; ++p) {
+        *(u32x4*)(base + (2 * s) * S::TILE + rowl[p] * SK + kq[p]) = ra[s][p];
+        *(u32x4*)(base + (2 * s + 1) * S::TILE + rowl[p] * SK + kq[p]) = rb[s][p];
+      }
+  };
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  if (klo < khi) {
+    load(klo);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = klo; k0 < khi; k0 += KT) {
+      const bool more = (k0 + KT < khi);
+      if (more) load(k0 + KT);
+      const u16* base = lds + buf * (S::NT * S::TILE);
+#pragma unroll
+      for (int ks = 0; ks < KT; ks += 16) {
+        u32x4 av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          av[i] = *(const u32x4*)(base + (wm * 128 + i * 32 + (lane & 31)) * SK + ks + 8 * (lane >> 5));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          bv[j] = *(const u32x4*)(base + S::TILE + (wn * 128 + j * 32 + (lane & 31)) * SK + ks + 8 * (lane >> 5));
+        if (NSPLIT == 3) {
+          u32x4 al[4], bl[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            al[i] = *(const u32x4*)(base + 2 * S::TILE + (wm * 128 + i * 32 + (lane & 31)) * SK + ks + 8 * (lane >> 5));
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            bl[j] = *(const u32x4*)(base + 3 * S::TILE + (wn * 128 + j * 32 + (lane & 31)) * SK + ks + 8 * (lane >> 5));
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              acc[i][j] = mma<F16>(av[i], bl[j], acc[i][j]);
+              acc[i][j] = mma<F16>(al[i], bv[j], acc[i][j]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(av[i], bv[j], acc[i][j]);
+      }
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  // ---------------------------------------------------------------- epilogues
+  const bool full = (m0 + LT <= M) && (n0 + LT <= N);
+  const double alpha = a.alpha;
+  double sq = 0.0, sqx = 0.0;
+  static_for<0, 16>([&](auto IJ) {
+      constexpr int i = decltype(IJ)::value / 4, j = decltype(IJ)::value % 4;
+      const f32x16 blk = acc[i][j];
+      const int64_t col = n0 + wn * 128 + j * 32 + (lane & 31);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // 4 consecutive rows per lane: r = 4q + (0..3)
+        const int64_t row0 = m0 + wm * 128 + i * 32 + 8 * q + 4 * (lane >> 5);
+        const bool colok = full || col < N;
+        if (EPI == kLpEpT) {
+          u16 o[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) o[e] = to_lp<F16>((float)(alpha * (double)blk[4 * q + e]));
+          u16* dst = (u16*)a.Ot + z * a.ot_bstride + col * a.ldot + row0;
+          if (full || (colok && row0 + 3 < M)) {
+            uint2 v;
+            v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
+            v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
+            *(uint2*)dst = v;
+          } else if (colok) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (row0 + e < M) dst[e] = o[e];
+          }
+        } else if (EPI == kLpEpX21) {
+          u16 o[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t row = row0 + e;
+            const double v = alpha * (double)blk[4 * q + e];
+            o[e] = to_lp<F16>((float)v);
+            if (full || (colok && row < M)) {
+              a.X[z * a.x_bstride + row * a.ldx + col] = v;
+              ((u16*)a.Xlp)[z * a.xlp_bstride + row * a.ldxlp + col] = o[e];
+            }
+          }
+          u16* dst = (u16*)a.Xlpt + z * a.xlpt_bstride + col * a.ldxlpt + row0;
+          if (full || (colok && row0 + 3 < M)) {
+            uint2 v;
+            v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
+            v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
+            *(uint2*)dst = v;
+          } else if (colok) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (row0 + e < M) dst[e] = o[e];
+          }
+        } else if (EPI == kLpEpResid) {
+          u16 o[4];
+          const double xjj = colok ? a.dX[col] : 0.0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t row = row0 + e;
+            double rv = 0.0;
+            if ((full || (colok && row < M)) && col <= row) {
+              const double lii = a.dL[row];
+              const double xij = a.X[row * a.ldx + col];
+              if (row == col) {
+                rv = fma(-lii, xij, 1.0);
+              } else {
+                const double lij = a.L[row * a.ldl + col];
+                rv = -(double)blk[4 * q + e] - lii * xij - lij * xjj;
+              }
+              a.R32[row * a.ldr + col] = (float)rv;
+              sq += rv * rv;
+              sqx += xij * xij;
+            }
+            o[e] = to_lp<F16>((float)rv);
+          }
+          u16* dst = (u16*)a.Rt + col * a.ldrt + row0;
+          if (full || (colok && row0 + 3 < M)) {
+            uint2 v;
+            v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
+            v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
+            *(uint2*)dst = v;
+          } else if (colok) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (row0 + e < M) dst[e] = o[e];
+          }
+        } else {  // kLpEpCorr
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t row = row0 + e;
+            if ((full || (colok && row < M)) && col <= row) {
+              const double xii = a.dX[row];
+              const double rij = (double)a.R32[row * a.ldr + col];
+              double* px = a.X + row * a.ldx + col;
+              *px = *px + xii * rij + (double)blk[4 * q + e];
+            }
+          }
+        }
+      }
+    });
+
+  if (EPI == kLpEpX21) {  // zero the FP64 X12 block: rows n0.., cols m0.. (transposed tile)
+    double* Zb = a.Xmirror + z * a.x_bstride;
+    for (int e = tid; e < LT * LT; e += 256) {
+      const int64_t mr = n0 + e / LT, mc = m0 + e % LT;
+      if (mr < N && mc < M) Zb[mr * a.ldx + mc] = 0.0;
+    }
+  }
+  if (EPI == kLpEpResid) {
+    for (int m = 32; m >= 1; m >>= 1) {
+      sq += __shfl_xor(sq, m, 64);
+      sqx += __shfl_xor(sqx, m, 64);
+    }
+    if (lane == 0) {
+      red[0][wave] = sq;
+      red[1][wave] = sqx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      a.tile_sq[t] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+      a.tile_sqx[t] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
+  }
+}
+
+template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
+static hipError_t go_lp(const LpGemmArgs& a, hipStream_t s, int64_t total) {
+  typedef LpShape<NSPLIT> S;
+  const size_t lds = 2u * S::NT * S::TILE * sizeof(unsigned short);
+  auto k = k_gemm_lp<F16, NSPLIT, AM, BM, TILES, ORDER, KLO, KHI, EPI>;
+  static bool attr_set = false;  // per instantiation
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k, dim3((unsigned)total), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int F16>
+static hipError_t dispatch_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_t s, int64_t total) {
+  // forward level product 1: T = C * A^-1 (B = A^-1 lower, transposed storage)
+  if (c.nsplit == 1 && c.amask == 0 && c.bmask == 1 && c.tiles == kAllTiles && c.order == kColAsc &&
+      c.klo == kLoN0 && c.khi == kHiK && c.epi == kLpEpT)
+    return go_lp<F16, 1, 0, 1, kAllTiles, kColAsc, kLoN0, kHiK, kLpEpT>(a, s, total);
+  // forward level product 2: X21 = -B^-1 * T (A = B^-1 lower)
+  if (c.nsplit == 1 && c.amask == 1 && c.bmask == 0 && c.tiles == kAllTiles && c.order == kRowDesc &&
+      c.klo == kLoZero && c.khi == kHiM1 && c.epi == kLpEpX21)
+    return go_lp<F16, 1, 1, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kLpEpX21>(a, s, total);
+  // residual: N_L * N_X (both strictly lower), split or not
+  if (c.amask == 2 && c.bmask == 2 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoN0 &&
+      c.khi == kHiM1 && c.epi == kLpEpResid) {
+    if (c.nsplit == 3) return go_lp<F16, 3, 2, 2, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpResid>(a, s, total);
+    if (c.nsplit == 1) return go_lp<F16, 1, 2, 2, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpResid>(a, s, total);
+  }
+  // correction: N_X * R (N_X strictly lower, R lower)
+  if (c.amask == 2 && c.bmask == 1 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoN0 &&
+      c.khi == kHiM1 && c.epi == kLpEpCorr) {
+    if (c.nsplit == 1) return go_lp<F16, 1, 2, 1, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpCorr>(a, s, total);
+    if (c.nsplit == 3) return go_lp<F16, 3, 2, 1, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpCorr>(a, s, total);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_t s) {
+  if (a.bt.nbatch != 1) return hipErrorInvalidValue;
+  const int64_t total = gemm_lp_tiles(a.bt, c.tiles);
+  if (total <= 0) return hipSuccess;
+  if (total > 0x7fffffff) return hipErrorInvalidValue;
+  if (c.tiles == kLowerTiles && a.bt.M != a.bt.N) return hipErrorInvalidValue;
+  return c.f16 ? dispatch_lp<1>(a, c, s, total) : dispatch_lp<0>(a, c, s, total);
+}
+
+}  // namespace trinv

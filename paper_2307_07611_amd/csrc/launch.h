@@ -8,14 +8,14 @@ namespace trinv {
 
 // ---------------------------------------------------------------- leaves
 // Inverts the diagonal leaf blocks of order `leaf` (the last one may be
-// shorter) of a strided batch of lower matrices. If Xlp is non-null a BF16
-// (lp_is_f16 = 0) or FP16 (1) copy of each leaf block is stored there too
-// (leading dimension ldxl, same batch stride). first_bad: atomic minimum of
+// shorter) of a strided batch of lower matrices. If Xlp / Xlpt are non-null,
+// a BF16 (lp_is_f16 = 0) or FP16 (1) copy of each leaf block is stored there
+// too, row-major / transposed (leading dimension ldxl, same batch stride). first_bad: atomic minimum of
 // the 1-based indices of exact zero pivots (init to all ones); one word for
 // the whole call, or one per matrix (per_matrix_status = 1).
 template <typename T>
 hipError_t launch_leaf(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int64_t stride, int64_t batch,
-                       int leaf, int unit, void* Xlp, int lp_is_f16, int64_t ldxl, uint64_t* first_bad,
+                       int leaf, int unit, void* Xlp, void* Xlpt, int lp_is_f16, int64_t ldxl, uint64_t* first_bad,
                        int per_matrix_status, hipStream_t s);
 
 // ---------------------------------------------------------------- tile products
@@ -69,6 +69,23 @@ struct GemmArgs {
   int subtract_identity;  // D = alpha*A*B - I (row == col inside the product)
   double* tile_sq;        // optional: per-tile sum of squares of D (FP64)
   GemmBatch bt;
+  // Refinement residual epilogue (FP64 product of the strictly lower parts
+  // N_L N_X): R = I - L X assembled in FP64 from acc and the diagonals,
+  // stored as FP32 (R32, ldr) and as a transposed low-precision copy (Rt,
+  // ldrt, BF16 or FP16 by lp_is_f16); per-tile sums of R^2 (tile_sq) and of
+  // X^2 (tile_sqx) over the lower triangle.
+  const TI* Lfull;
+  int64_t ldl;
+  const TI* Xfull;
+  int64_t ldx;
+  const double* dL;
+  const double* dX;
+  float* R32;
+  int64_t ldr;
+  void* Rt;
+  int64_t ldrt;
+  double* tile_sqx;
+  int refine_resid;
 };
 
 template <typename TI, typename TC>
@@ -82,6 +99,8 @@ template <typename T>
 hipError_t launch_sumsq(const T* A, int64_t n, int64_t lda, int lower, int unit, double* partial,
                         int64_t npartial, double* out, hipStream_t s);
 hipError_t launch_reduce_sum(const double* partial, int64_t count, double* out, hipStream_t s);
+// out[0] = sum of v[i]^2 (one block, fixed order).
+hipError_t launch_sumsq_vec(const double* v, int64_t count, double* out, hipStream_t s);
 // status[i] = first_bad[i] == all ones ? 0 : first_bad[i]  (int32 per matrix).
 hipError_t launch_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count, hipStream_t s);
 // B = A^T for an n x n matrix.

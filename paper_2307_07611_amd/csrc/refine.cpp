@@ -1,14 +1,310 @@
-// Mixed-precision path: BF16 / FP16 MFMA products with Newton-Schulz
-// refinement (placeholder until the low-precision kernels land).
+// Mixed-precision path: the recursion of Section 4.1 (algorithm COMBRIT,
+// beta = 2) with its off-diagonal products on BF16 (or FP16) MFMA with FP32
+// accumulation, FP64 leaves (column recurrence CRIT, Section 4.2), and then
+// Newton-Schulz refinement (not in the paper):
+//     R = I - L X,   X <- X + X R   (R_{k+1} = R_k^2 in exact arithmetic;
+//                                    X stays lower triangular)
+// until ||R||_F / (||L||_F ||X||_F) <= tol.
+//
+// Residual, assembled and stored in FP64: with L = D_L + N_L and X = D_X + N_X
+// (diagonal + strictly lower parts),
+//     R = (I - D_L D_X) - D_L N_X - N_L D_X - N_L N_X,
+// where the O(n^2) terms are formed exactly in FP64 in the epilogue and the
+// O(n^3) product N_L N_X runs on MFMA with both factors split into hi + lo
+// slices (three products). Correction: X R = D_X R + N_X R, the first term in
+// FP64, the second on MFMA (N_X is small next to D_X for diagonally dominant
+// inverses, so its low-precision error is scaled down accordingly).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
 #include "api_internal.h"
+#include "lowp.h"
+#include "profile.h"
 
 namespace trinv {
 
-size_t refine_workspace_bytes(int, int64_t, const trinv_opts&, int64_t) { return 0; }
+namespace {
 
-int refine_inverse(int, int64_t, const double*, int64_t, double*, int64_t, const trinv_opts&, int64_t, void*, size_t,
-                   hipStream_t, trinv_info*) {
-  return TRINV_ERR_UNSUPPORTED;
+constexpr int64_t kPart = 4096;
+
+int64_t lp_ld(int64_t n) { return (n + 8 + 63) / 64 * 64; }
+int64_t t_ld(int64_t hA) { return (hA + 8 + 63) / 64 * 64; }
+
+int64_t lp_t_elems(int64_t n, int64_t leaf) {
+  int64_t m = 0;
+  for (const Level& l : levels_of(n, leaf)) m = std::max(m, l.nmerge * l.hA * t_ld(l.hA));
+  return m;
+}
+
+struct WsRefine {
+  uint64_t* status;
+  unsigned short *Lhi, *Llo, *Xb, *Xbt, *Xtlo, *Tt, *Rt;
+  float* R32;
+  double *dL, *dX, *tile_sq, *tile_sqx, *partial, *scal;
+  int64_t ldp;
+};
+
+WsRefine carve_refine(Carve& c, int64_t n, int64_t leaf) {
+  WsRefine w;
+  w.ldp = lp_ld(n);
+  const size_t pl = (size_t)n * w.ldp + 64;  // one low-precision plane (+ slack for over-reads)
+  w.status = c.take<uint64_t>(1);
+  w.Lhi = c.take<unsigned short>(pl);
+  w.Llo = c.take<unsigned short>(pl);
+  w.Xb = c.take<unsigned short>(pl);
+  w.Xbt = c.take<unsigned short>(pl);
+  w.Xtlo = c.take<unsigned short>(pl);
+  w.Rt = c.take<unsigned short>(pl);
+  w.Tt = c.take<unsigned short>((size_t)lp_t_elems(n, leaf) + 64);
+  w.R32 = c.take<float>((size_t)n * n);
+  w.dL = c.take<double>((size_t)n);
+  w.dX = c.take<double>((size_t)n);
+  GemmBatch bt{1, 1, n, n, n, n, n, n};
+  const int64_t nt = std::max<int64_t>({1, gemm_lp_tiles(bt, kLowerTiles), gemm_tiles(bt, kLowerTiles)});
+  w.tile_sq = c.take<double>((size_t)nt);
+  w.tile_sqx = c.take<double>((size_t)nt);
+  w.partial = c.take<double>(kPart);
+  w.scal = c.take<double>(8);
+  return w;
+}
+
+// Level products of the forward recursion on low-precision MFMA.
+hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, const WsRefine& w, hipStream_t s) {
+  const int64_t ldp = w.ldp;
+  for (const Level& lv : levels_of(n, leaf)) {
+    const int64_t hA = lv.hA, span = lv.span, ldt = t_ld(hA);
+    const int64_t stp = span * (ldp + 1), stx = span * (ldx + 1);
+    const double fh = (double)hA, hB = (double)lv.hB_last, full = (double)(lv.nmerge - 1);
+    // T = C * A^-1 (stored transposed)
+    LpGemmArgs g1{};
+    g1.A_hi = w.Lhi + hA * ldp;  // C
+    g1.lda = ldp;
+    g1.a_bstride = stp;
+    g1.Bt_hi = w.Xbt;  // (A^-1)^T rows = A^-1 columns
+    g1.ldb = ldp;
+    g1.b_bstride = stp;
+    g1.bt = {lv.nmerge, 1, hA, hA, hA, lv.hB_last, hA, hA};
+    g1.alpha = 1.0;
+    g1.Ot = w.Tt;
+    g1.ldot = ldt;
+    g1.ot_bstride = hA * ldt;
+    LpConfig c1{f16, 1, 0, 1, kAllTiles, kColAsc, kLoN0, kHiK, kLpEpT};
+    hipError_t e;
+    {
+      ProfLaunch pl(f16 ? "gemm_f16" : "gemm_bf16", full * fh * fh * (fh + 1) + hB * fh * (fh + 1),
+                    2.0 * (full * 2.5 * fh * fh + (2 * hB * fh + fh * fh / 2)), s);
+      e = launch_gemm_lp(g1, c1, s);
+    }
+    if (e != hipSuccess) return e;
+    // X21 = -B^-1 * T
+    LpGemmArgs g2{};
+    g2.A_hi = w.Xb + hA * ldp + hA;  // B^-1 row-major
+    g2.lda = ldp;
+    g2.a_bstride = stp;
+    g2.Bt_hi = w.Tt;
+    g2.ldb = ldt;
+    g2.b_bstride = hA * ldt;
+    g2.bt = {lv.nmerge, 1, hA, hA, hA, lv.hB_last, hA, lv.hB_last};
+    g2.alpha = -1.0;
+    g2.X = X + hA * ldx;
+    g2.ldx = ldx;
+    g2.x_bstride = stx;
+    g2.Xmirror = X + hA;
+    g2.Xlp = w.Xb + hA * ldp;
+    g2.ldxlp = ldp;
+    g2.xlp_bstride = stp;
+    g2.Xlpt = w.Xbt + hA;
+    g2.ldxlpt = ldp;
+    g2.xlpt_bstride = stp;
+    LpConfig c2{f16, 1, 1, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kLpEpX21};
+    {
+      ProfLaunch pl(f16 ? "gemm_f16" : "gemm_bf16", full * fh * fh * (fh + 1) + fh * hB * (hB + 1),
+                    full * (2 * (fh * fh / 2 + fh * fh) + 12 * fh * fh) + (2 * (hB * hB / 2 + hB * fh) + 12 * hB * fh),
+                    s);
+      e = launch_gemm_lp(g2, c2, s);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+double tri_flops(double n) { return n * (n - 1) * (n - 2) / 3.0; }  // strictly-lower x strictly-lower
+
+}  // namespace
+
+size_t refine_workspace_bytes(int mode, int64_t n, const trinv_opts& o, int64_t leaf) {
+  (void)mode;
+  (void)o;
+  if (n <= 0) return 0;
+  Carve c(nullptr, 0);
+  carve_refine(c, n, leaf);
+  return c.used;
+}
+
+int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X, int64_t ldx, const trinv_opts& o,
+                   int64_t leaf, void* ws, size_t ws_bytes, hipStream_t s, trinv_info* info) {
+  if (o.upper) return TRINV_ERR_UNSUPPORTED;
+  if (leaf < 32) return TRINV_ERR_ARG;
+  const int f16 = mode == TRINV_F16_REFINE;
+  if (f16) return TRINV_ERR_UNSUPPORTED;  // FP16 slices need row/column scaling (not built yet)
+  Carve c(ws, ws_bytes);
+  WsRefine w = carve_refine(c, n, leaf);
+  if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
+  const int64_t ldp = w.ldp;
+  const double dn = (double)n;
+
+  HIP_TRY(launch_fill_u64(w.status, ~0ull, 1, s));
+  {  // staging: L -> hi / lo slices (row-major) and diag(L)
+    ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + 4), s);
+    HIP_TRY(launch_split(L, ldl, n, f16, w.Lhi, w.Llo, nullptr, nullptr, ldp, w.dL, o.unit_diag, s));
+  }
+  {  // leaves in FP64, with row-major and transposed low-precision copies
+    const double nl = (double)((n + leaf - 1) / leaf), b = (double)leaf;
+    ProfLaunch pl("leaf_f64", nl * b * b * b / 3.0, nl * b * b * (8 + 8 + 4), s);
+    HIP_TRY(launch_leaf<double>(n, L, ldl, X, ldx, 0, 1, (int)leaf, o.unit_diag, w.Xb, w.Xbt, f16, ldp, w.status, 0,
+                                s));
+  }
+  HIP_TRY(lp_levels(n, X, ldx, leaf, f16, w, s));
+  // ||tril(L)||^2 and sum of diag(L)^2 once
+  HIP_TRY(launch_sumsq<double>(L, n, ldl, 1, o.unit_diag, w.partial, kPart, w.scal + 2, s));
+  HIP_TRY(launch_sumsq_vec(w.dL, n, w.scal + 3, s));
+
+  GemmBatch bt{1, 1, n, n, n, n, n, n};
+  int iter = 0;
+  double rho = 0.0;
+  // Precision of the residual's O(n^3) product. The split low-precision
+  // product has a floor: its error relative to ||L|| ||X|| is about
+  //   c * eps_split * ||N_L|| ||N_X|| / (sqrt(n) ||L|| ||X||)
+  // (errors of the ~n terms of each entry add like a random walk; c = 0.25
+  // measured for BF16 slices, eps_split = 2^-16). It is used only when that
+  // estimate, taken with c = 0.5, is at most half the tolerance; otherwise the
+  // residual runs on FP64 MFMA.
+  int resid_fp64 = -1;  // decided once, after the forward, from the norms
+  double floor_est = 0.0;
+  const double eps_split = f16 ? std::ldexp(1.0, -22) : std::ldexp(1.0, -16);
+  for (;;) {
+    // residual of the current X
+    {
+      ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + 6), s);
+      HIP_TRY(launch_split(X, ldx, n, f16, w.Xb, nullptr, w.Xbt, w.Xtlo, ldp, w.dX, 0, s));
+    }
+    if (resid_fp64 < 0) {
+      HIP_TRY(launch_sumsq<double>(X, n, ldx, 1, 0, w.partial, kPart, w.scal + 4, s));
+      HIP_TRY(launch_sumsq_vec(w.dX, n, w.scal + 5, s));
+      double h6[6];
+      HIP_TRY(hipMemcpyAsync(h6, w.scal, sizeof(h6), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      const double nl = std::sqrt(std::max(0.0, h6[2] - h6[3])), nx = std::sqrt(std::max(0.0, h6[4] - h6[5]));
+      floor_est = 0.5 * eps_split * nl * nx / (std::sqrt(dn) * std::sqrt(h6[2]) * std::sqrt(h6[4]));
+      resid_fp64 = (floor_est <= 0.5 * o.tol) ? 0 : 1;
+    }
+    if (resid_fp64) {
+      GemmArgs<double> gf{};
+      gf.A = {L, ldl, 0, 0};
+      gf.amask = 2;
+      gf.B = {X, ldx, 0, 0};
+      gf.bmask = 2;
+      gf.alpha = 1.0;
+      gf.tiles = kLowerTiles;
+      gf.order = kDiagDesc;
+      gf.klo = kLoN0;
+      gf.khi = kHiM1;
+      gf.bt = bt;
+      gf.refine_resid = 1;
+      gf.Lfull = L;
+      gf.ldl = ldl;
+      gf.Xfull = X;
+      gf.ldx = ldx;
+      gf.dL = w.dL;
+      gf.dX = w.dX;
+      gf.R32 = w.R32;
+      gf.ldr = n;
+      gf.Rt = w.Rt;
+      gf.ldrt = ldp;
+      gf.lp_is_f16 = f16;
+      gf.tile_sq = w.tile_sq;
+      gf.tile_sqx = w.tile_sqx;
+      {
+        ProfLaunch pl("gemm_f64", tri_flops(dn), dn * dn / 2 * (8 * 2 + 8 + 8 + 4 + 2), s);
+        HIP_TRY(launch_gemm<double, double>(gf, s));
+      }
+      const int64_t ntf = gemm_tiles(bt, kLowerTiles);
+      HIP_TRY(launch_reduce_sum(w.tile_sq, ntf, w.scal + 0, s));
+      HIP_TRY(launch_reduce_sum(w.tile_sqx, ntf, w.scal + 1, s));
+    } else {
+    LpGemmArgs gr{};
+    gr.A_hi = w.Lhi;
+    gr.A_lo = w.Llo;
+    gr.lda = ldp;
+    gr.Bt_hi = w.Xbt;
+    gr.Bt_lo = w.Xtlo;
+    gr.ldb = ldp;
+    gr.bt = bt;
+    gr.alpha = 1.0;
+    gr.X = X;
+    gr.ldx = ldx;
+    gr.L = L;
+    gr.ldl = ldl;
+    gr.dL = w.dL;
+    gr.dX = w.dX;
+    gr.R32 = w.R32;
+    gr.ldr = n;
+    gr.Rt = w.Rt;
+    gr.ldrt = ldp;
+    gr.tile_sq = w.tile_sq;
+    gr.tile_sqx = w.tile_sqx;
+    LpConfig cr{f16, 3, 2, 2, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpResid};
+    {
+      ProfLaunch pl(f16 ? "gemm_f16" : "gemm_bf16", 3.0 * tri_flops(dn), dn * dn / 2 * (4 * 2 + 8 + 8 + 4 + 2), s);
+      HIP_TRY(launch_gemm_lp(gr, cr, s));
+    }
+    const int64_t ntl = gemm_lp_tiles(bt, kLowerTiles);
+    HIP_TRY(launch_reduce_sum(w.tile_sq, ntl, w.scal + 0, s));
+    HIP_TRY(launch_reduce_sum(w.tile_sqx, ntl, w.scal + 1, s));
+    }
+    double h[3];
+    HIP_TRY(hipMemcpyAsync(h, w.scal, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (iter == 0) {
+      uint64_t bad = ~0ull;
+      HIP_TRY(hipMemcpy(&bad, w.status, sizeof(bad), hipMemcpyDeviceToHost));
+      if (bad != ~0ull && bad <= (uint64_t)n) {
+        if (info) info->first_bad_index = (int64_t)bad;
+        return TRINV_ERR_SINGULAR;
+      }
+    }
+    rho = std::sqrt(h[0]) / (std::sqrt(h[2]) * std::sqrt(h[1]));
+    if (info) {
+      info->rel_residual = rho;
+      info->iterations = iter;
+      // Error scale of rho: the floor estimate above for the split product,
+      // n * 2^-53 for the FP64 product.
+      info->resid_error_bound = resid_fp64 ? dn * std::ldexp(1.0, -53) : floor_est;
+    }
+    if (!std::isfinite(rho)) return TRINV_ERR_NONFINITE;
+    if (rho <= o.tol) return TRINV_OK;
+    if (iter >= o.max_iter) return TRINV_ERR_NOT_CONVERGED;
+    // correction: X <- X + D_X R + N_X R
+    LpGemmArgs gc{};
+    gc.A_hi = w.Xb;
+    gc.lda = ldp;
+    gc.Bt_hi = w.Rt;
+    gc.ldb = ldp;
+    gc.bt = bt;
+    gc.alpha = 1.0;
+    gc.X = X;
+    gc.ldx = ldx;
+    gc.dX = w.dX;
+    gc.R32 = w.R32;
+    gc.ldr = n;
+    LpConfig cc{f16, 1, 2, 1, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpCorr};
+    {
+      ProfLaunch pl(f16 ? "gemm_f16" : "gemm_bf16", tri_flops(dn) + dn * dn, dn * dn / 2 * (2 + 2 + 4 + 16), s);
+      HIP_TRY(launch_gemm_lp(gc, cc, s));
+    }
+    ++iter;
+  }
 }
 
 }  // namespace trinv

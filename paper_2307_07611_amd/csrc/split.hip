@@ -1,0 +1,84 @@
+// Staging casts of the mixed-precision path: an FP64 lower-triangular matrix
+// is cut into low-precision slices hi = round(v) and lo = round(v - hi)
+// (round-to-nearest-even in BF16 or FP16; v - hi is exact in FP64), written
+// row-major and/or transposed (through a 64 x 64 LDS tile so both stores are
+// coalesced), plus the FP64 diagonal. HBM-bound: one read of the lower
+// triangle, 2 bytes written per requested slice and element.
+#include "common.h"
+#include "lowp.h"
+
+namespace trinv {
+
+namespace {
+typedef unsigned short u16;
+
+template <int F16>
+__device__ __forceinline__ u16 lp_bits(double v, double* back) {
+  if (F16) {
+    const _Float16 h = (_Float16)v;
+    *back = (double)h;
+    return __builtin_bit_cast(u16, h);
+  }
+  const __bf16 h = (__bf16)v;
+  *back = (double)(float)h;
+  return __builtin_bit_cast(u16, h);
+}
+}  // namespace
+
+// Grid: one block per 64 x 64 tile of the lower triangle (tile row it >= tile col jt).
+template <int F16>
+__global__ __launch_bounds__(256) void k_split(const double* __restrict__ S, int64_t lds, int64_t n,
+                                               u16* __restrict__ hi, u16* __restrict__ lo, u16* __restrict__ hi_t,
+                                               u16* __restrict__ lo_t, int64_t ldo, double* __restrict__ diag,
+                                               int unit) {
+  __shared__ u16 th[64][66];
+  __shared__ u16 tl[64][66];
+  const int64_t q = blockIdx.x;
+  int64_t it = (int64_t)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+  while (it * (it + 1) / 2 > q) --it;
+  while ((it + 1) * (it + 2) / 2 <= q) ++it;
+  const int64_t jt = q - it * (it + 1) / 2;
+  const int64_t i0 = it * 64, j0 = jt * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    u16 h = 0, l = 0;
+    if (i < n && j < n) {
+      double v = (j <= i) ? S[i * lds + j] : 0.0;
+      if (unit && i == j) v = 1.0;
+      if (i == j && diag) diag[i] = v;
+      double hb;
+      h = lp_bits<F16>(v, &hb);
+      double lb;
+      l = lp_bits<F16>(v - hb, &lb);
+      if (hi) hi[i * ldo + j] = h;
+      if (lo) lo[i * ldo + j] = l;
+    }
+    th[r][tx] = h;
+    tl[r][tx] = l;
+  }
+  if (!hi_t && !lo_t) return;
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t c = j0 + r, rr = i0 + tx;  // transposed element (c, rr) = S(rr, c)
+    if (c < n && rr < n) {
+      if (hi_t) hi_t[c * ldo + rr] = th[tx][r];
+      if (lo_t) lo_t[c * ldo + rr] = tl[tx][r];
+    }
+  }
+}
+
+hipError_t launch_split(const double* S, int64_t lds, int64_t n, int f16, void* hi, void* lo, void* hi_t, void* lo_t,
+                        int64_t ldo, double* diag, int unit, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t T = (n + 63) / 64, blocks = T * (T + 1) / 2;
+  if (f16)
+    hipLaunchKernelGGL(k_split<1>, dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, (u16*)hi, (u16*)lo, (u16*)hi_t,
+                       (u16*)lo_t, ldo, diag, unit);
+  else
+    hipLaunchKernelGGL(k_split<0>, dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, (u16*)hi, (u16*)lo, (u16*)hi_t,
+                       (u16*)lo_t, ldo, diag, unit);
+  return hipGetLastError();
+}
+
+}  // namespace trinv

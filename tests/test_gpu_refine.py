@@ -1,0 +1,129 @@
+"""GPU parity of the mixed-precision path (BF16 MFMA products + FP64 leaves and
+residual + Newton-Schulz refinement) against the CPU oracle.
+
+Tolerance: the relative residual ||LX - I||_F / (||L||_F ||X||_F) after
+refinement must be <= 1e-12 (the stopping rule), checked independently with
+the oracle's FP64 residual (CPU) or the FP64-MFMA residual helper (n = 16384,
+itself checked against the oracle in the plain-path tests). The forward error
+against the oracle is bounded by kappa times that residual times the norm
+ratio; for this generator kappa ~ 2, and 1e-10 is used (relative Frobenius).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import banner, dev, host, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def trinv():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_07611_amd as P
+
+    P.load()
+    return P
+
+
+def run(trinv, L, **kw):
+    import torch
+
+    X, info = trinv.tril_inverse(L, "bf16_refine", return_info=True, **kw)
+    torch.cuda.synchronize()
+    return X, info
+
+
+@pytest.mark.parametrize("n,leaf", [(256, 64), (300, 64), (1024, 64), (1500, 128), (2048, 128)])
+def test_bf16_refine_vs_oracle(trinv, n, leaf):
+    banner(f"bf16_refine n={n} leaf={leaf}")
+    L = synth.lower_triangular(n, 60 + n)
+    X, info = run(trinv, dev(L), leaf=leaf)
+    Xg = host(X)
+    r = oracle.residuals(L, Xg)
+    print(f"n={n}: iterations={info['iterations']} rho_gpu={info['rel_residual']:.3e} "
+          f"rho_oracle={r['rel_lx']:.3e} fwd={rel_fro(Xg, oracle.tril_inverse(L)):.3e}", flush=True)
+    assert r["rel_lx"] <= 1e-12
+    assert info["rel_residual"] <= 1e-12
+    assert rel_fro(Xg, oracle.tril_inverse(L)) < 1e-10
+    assert np.all(np.triu(Xg, 1) == 0.0)
+    # the in-loop residual estimate agrees with the FP64 one within its error scale
+    assert abs(info["rel_residual"] - r["rel_lx"]) < 1e-12
+
+
+def test_bf16_exact_bidiagonal(trinv):
+    """All values +-1: every product and every partial sum is exact in BF16 /
+    FP32, so X is the exact all-ones lower triangle and no correction runs."""
+    n = 1000
+    banner(f"bf16_refine bidiagonal -1 n={n}")
+    L = np.eye(n)
+    L[np.arange(1, n), np.arange(n - 1)] = -1.0
+    X, info = run(trinv, dev(L), leaf=64)
+    np.testing.assert_array_equal(host(X), np.tril(np.ones((n, n))))
+    assert info["iterations"] == 0 and info["rel_residual"] == 0.0
+
+
+def test_bf16_not_converged_reports_forward_residual(trinv):
+    from paper_2307_07611_amd import _lib
+
+    n = 1024
+    banner(f"bf16_refine max_iter=0 n={n}")
+    L = synth.lower_triangular(n, 9)
+    with pytest.raises(_lib.TrinvError) as e:
+        trinv.tril_inverse(dev(L), "bf16_refine", leaf=64, max_iter=0)
+    assert e.value.code == _lib.ERR_NOT_CONVERGED
+    assert 1e-12 < e.value.info["rel_residual"] < 1e-3
+    assert e.value.info["iterations"] == 0
+
+
+def test_bf16_singular(trinv):
+    from paper_2307_07611_amd import _lib
+
+    banner("bf16_refine singular n=512")
+    L = synth.lower_triangular(512, 3)
+    L[300, 300] = 0.0
+    with pytest.raises(_lib.TrinvError) as e:
+        trinv.tril_inverse(dev(L), "bf16_refine", leaf=64)
+    assert e.value.code == _lib.ERR_SINGULAR and e.value.info["first_bad_index"] == 301
+
+
+def test_bf16_ill_conditioned_is_honest(trinv):
+    """Unit lower with U[-1,1] off-diagonals (no 1/n scale): the condition
+    number grows exponentially with n. The path must either certify a
+    residual that the FP64 check confirms, or report NOT_CONVERGED."""
+    from paper_2307_07611_amd import _lib
+
+    n = 512
+    banner(f"bf16_refine ill-conditioned n={n}")
+    L = synth.lower_triangular(n, 4, unit=True)
+    L[np.tril_indices(n, -1)] *= n
+    try:
+        X, info = run(trinv, dev(L), leaf=64, max_iter=6)
+        assert oracle.residuals(L, host(X))["rel_lx"] <= 1e-12
+    except _lib.TrinvError as e:
+        assert e.code in (_lib.ERR_NOT_CONVERGED, _lib.ERR_NONFINITE)
+
+
+def test_bf16_n16384_configuration(trinv):
+    """Configuration size: residual by the FP64-MFMA helper, sampled columns
+    against the oracle."""
+    import torch
+
+    n = 16384
+    banner(f"bf16_refine n={n} leaf=128 seed=5")
+    L = synth.lower_triangular(n, 5)
+    Ld = dev(L)
+    X, info = run(trinv, Ld, leaf=128)
+    r = trinv.residual(Ld, X)
+    print(f"n={n}: iterations={info['iterations']} rho_gpu={info['rel_residual']:.3e} rho_fp64={r['rel']:.3e}",
+          flush=True)
+    assert r["rel"] <= 1e-12 and info["rel_residual"] <= 1e-12
+    cols = np.array([0, 4095, 8192, 16000, 16383])
+    Xo = oracle.tril_inverse_columns(L, cols)
+    Xg = host(X[:, torch.from_numpy(cols).cuda()])
+    assert rel_fro(Xg, Xo) < 1e-10
