@@ -42,13 +42,17 @@ constexpr int LT = 256;  // workgroup tile (rows and columns)
 
 template <int NSPLIT>
 struct LpShape {
-  static constexpr int KT = NSPLIT == 1 ? 32 : 16;  // K per LDS stage
-  static constexpr int SK = KT + 8;                 // LDS row stride (elements)
-  static constexpr int TILE = LT * SK;              // elements of one staged operand tile
+  static constexpr int KT = NSPLIT == 1 ? 64 : 32;  // K per LDS stage
   static constexpr int NT = NSPLIT == 1 ? 2 : 4;    // staged tiles per stage
-  static constexpr int CHUNKS = LT * KT / 8;        // 16-byte chunks per tile
-  static constexpr int CPT = CHUNKS / 256;          // chunks per thread per tile
-  static constexpr int CPR = KT / 8;                // chunks per row
+  static constexpr int CPR = KT / 8;                // 16-byte chunks per tile row
+  static constexpr int TILE = LT * KT;              // elements of one staged tile (no padding)
+  static constexpr int RPI = 512 / KT;              // tile rows per 1 KB direct-load instruction
+  static constexpr int IPW = KT / 8;                // direct-load instructions per wave per tile
+  static constexpr int RSW = 128 / KT;              // rows per swizzle step
+  // Chunk position p of row r holds the row's k-chunk p ^ swz(r): 16
+  // consecutive rows read at one logical chunk hit 16 distinct bank groups.
+  static __device__ __forceinline__ int swz(int r) { return (r / RSW) % CPR; }
+  static_assert(32 % (RSW * CPR) == 0, "swizzle period must divide the 32-row fragment block");
 };
 
 typedef unsigned short u16;
@@ -116,7 +120,7 @@ int64_t gemm_lp_tiles(const GemmBatch& bt, int tiles) {
 template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
 __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   typedef LpShape<NSPLIT> S;
-  constexpr int KT = S::KT, SK = S::SK;
+  constexpr int KT = S::KT;
   extern __shared__ __attribute__((aligned(16))) u16 lds[];  // 2 stages x NT tiles x TILE elements
   __shared__ double red[2][4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -144,78 +148,80 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   if (KHI == kHiM1) khi = imin64(K, m0 + LT);
   klo = (klo / KT) * KT;
 
-  // Staging: chunk c = tid + 256 p of a 256 x KT tile -> row c / CPR, k offset 8 (c % CPR).
-  const u16* pa[NSPLIT == 1 ? 1 : 2][S::CPT];
-  const u16* pb[NSPLIT == 1 ? 1 : 2][S::CPT];
-  int rowl[S::CPT], kq[S::CPT];
-  const u16* Ahi = (const u16*)a.A_hi + z * a.a_bstride;
-  const u16* Bhi = (const u16*)a.Bt_hi + z * a.b_bstride;
-  const u16* Alo = NSPLIT == 3 ? (const u16*)a.A_lo + z * a.a_bstride : nullptr;
-  const u16* Blo = NSPLIT == 3 ? (const u16*)a.Bt_lo + z * a.b_bstride : nullptr;
+  // Staging by direct global -> LDS loads: instruction i of wave w fills
+  // tile rows [q RPI, (q+1) RPI), q = w IPW + i; lane L writes 16 bytes at
+  // LDS byte L*16 of that 1 KB block, i.e. row q RPI + L / CPR, chunk position
+  // L % CPR, and so loads the row's k-chunk (L % CPR) ^ swz(row). Rows beyond
+  // M (N) are clamped; they only feed outputs that are not stored.
+  const u16* tb[4];
+  tb[0] = (const u16*)a.A_hi + z * a.a_bstride;
+  tb[1] = (const u16*)a.Bt_hi + z * a.b_bstride;
+  tb[2] = NSPLIT == 3 ? (const u16*)a.A_lo + z * a.a_bstride : nullptr;
+  tb[3] = NSPLIT == 3 ? (const u16*)a.Bt_lo + z * a.b_bstride : nullptr;
+  uint32_t off[S::NT][S::IPW];  // byte offsets of this lane's source chunk, stage 0
 #pragma unroll
-  for (int p = 0; p < S::CPT; ++p) {
-    const int c = tid + 256 * p;
-    rowl[p] = c / S::CPR;
-    kq[p] = 8 * (c % S::CPR);
-    const int64_t ma = imin64(m0 + rowl[p], M - 1), nb = imin64(n0 + rowl[p], N - 1);
-    pa[0][p] = Ahi + ma * a.lda + klo + kq[p];
-    pb[0][p] = Bhi + nb * a.ldb + klo + kq[p];
-    if (NSPLIT == 3) {
-      pa[NSPLIT == 1 ? 0 : 1][p] = Alo + ma * a.lda + klo + kq[p];
-      pb[NSPLIT == 1 ? 0 : 1][p] = Blo + nb * a.ldb + klo + kq[p];
+  for (int tt = 0; tt < S::NT; ++tt) {
+    const bool isb = tt & 1;
+    const int64_t ld = isb ? a.ldb : a.lda;
+    const int64_t r0 = isb ? n0 : m0, rmax = (isb ? N : M) - 1;
+#pragma unroll
+    for (int i = 0; i < S::IPW; ++i) {
+      const int row = (wave * S::IPW + i) * S::RPI + lane / S::CPR;
+      const int chunk = (lane % S::CPR) ^ S::swz(row);
+      const int64_t grow = imin64(r0 + row, rmax);
+      off[tt][i] = (uint32_t)((grow * ld + klo + 8 * chunk) * 2);
     }
   }
-  constexpr int NS = NSPLIT == 1 ? 1 : 2;
-  u32x4 ra[NS][S::CPT], rb[NS][S::CPT];
-
-  auto load = [&](int64_t k0) {
-    bool guard = (k0 + KT > K);
-    if (AM != 0 && k0 + KT > m0 && k0 < m0 + LT) guard = true;
-    if (BM != 0 && k0 + KT > n0 && k0 < n0 + LT) guard = true;
+  auto issue = [&](int buf, int64_t kstage) {  // loads of the stage starting at klo + kstage
+    typedef __attribute__((address_space(3))) char lds_char;
+    lds_char* base = (lds_char*)lds + (size_t)buf * S::NT * S::TILE * 2;
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
+    for (int tt = 0; tt < S::NT; ++tt) {
+      const char* src = (const char*)tb[tt] + kstage * 2;
 #pragma unroll
-      for (int p = 0; p < S::CPT; ++p) {
-        ra[s][p] = *(const u32x4*)pa[s][p];
-        rb[s][p] = *(const u32x4*)pb[s][p];
-      }
-    if (guard) {
+      for (int i = 0; i < S::IPW; ++i)
+        __builtin_amdgcn_global_load_lds((const void*)(src + off[tt][i]),
+                                         (__attribute__((address_space(3))) void*)(base + tt * S::TILE * 2 +
+                                                                                   (wave * S::IPW + i) * 1024),
+                                         16, 0, 0);
+    }
+  };
+  // Fragment of tile tt for block blk at k step ks (16 wide): 8 elements of
+  // one tile row, read from its swizzled chunk position.
+  // The swizzle has a period of 16 rows, which divides 32, so it depends on
+  // lane & 31 only and the block offset folds into an immediate.
+  const int fsw = S::swz(lane & 31);
+  auto frag = [&](const u16* base, int tt, int ks, int blk) -> u32x4 {
+    const int row = ((tt & 1) ? wn : wm) * 128 + blk * 32 + (lane & 31);
+    const int chunk = ks / 8 + (lane >> 5);
+    return *(const u32x4*)(base + tt * S::TILE + row * S::KT + 8 * (chunk ^ fsw));
+  };
+  // Zero fill beyond K and the element masks, applied to a staged buffer in
+  // LDS (only for stages that reach the K edge or a masked diagonal): thread
+  // handles 16-byte chunk positions of the tiles.
+  auto mask_lds = [&](int buf, int64_t k0) {
+    u16* base = lds + buf * (S::NT * S::TILE);
+    constexpr int CH = LT * S::CPR;  // chunk positions per tile
 #pragma unroll
-      for (int p = 0; p < S::CPT; ++p) {
-        const int64_t kb = k0 + kq[p];
-        const int64_t ma = m0 + rowl[p], nb = n0 + rowl[p];
+    for (int tt = 0; tt < S::NT; ++tt) {
+      const bool isb = tt & 1;
+      const int64_t r0 = isb ? n0 : m0;
+      for (int c = tid; c < CH; c += 256) {
+        const int row = c / S::CPR, p = c % S::CPR;
+        const int64_t kb = k0 + 8 * (p ^ S::swz(row));
+        u32x4* ptr = (u32x4*)(base + tt * S::TILE + row * S::KT + 8 * p);
+        u32x4 v = *ptr;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int64_t k = kb + e;
-          const bool oka = (k < K) && lp_mask_ok<AM, true>(ma, k);
-          const bool okb = (k < K) && lp_mask_ok<BM, false>(nb, k);
+          const bool ok =
+              (k < K) && (isb ? lp_mask_ok<BM, false>(r0 + row, k) : lp_mask_ok<AM, true>(r0 + row, k));
           const unsigned sh = 16 * (e & 1);
-          const unsigned keep_a = oka ? 0xffffu << sh : 0u, keep_b = okb ? 0xffffu << sh : 0u;
-#pragma unroll
-          for (int s = 0; s < NS; ++s) {
-            ra[s][p][e >> 1] &= (keep_a | ~(0xffffu << sh));
-            rb[s][p][e >> 1] &= (keep_b | ~(0xffffu << sh));
-          }
+          v[e >> 1] &= (ok ? 0xffffffffu : ~(0xffffu << sh));
         }
+        *ptr = v;
       }
     }
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-#pragma unroll
-      for (int p = 0; p < S::CPT; ++p) {
-        pa[s][p] += KT;
-        pb[s][p] += KT;
-      }
-  };
-  auto store = [&](int buf) {
-    u16* base = lds + buf * (S::NT * S::TILE);
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-#pragma unroll
-      for (int p = 0; p < S::CPT; ++p) {
-        *(u32x4*)(base + (2 * s) * S::TILE + rowl[p] * SK + kq[p]) = ra[s][p];
-        *(u32x4*)(base + (2 * s + 1) * S::TILE + rowl[p] * SK + kq[p]) = rb[s][p];
-      }
   };
 
   f32x16 acc[4][4];
@@ -226,46 +232,99 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  if (klo < khi) {
-    load(klo);
-    store(0);
-    __syncthreads();
-    int buf = 0;
-    for (int64_t k0 = klo; k0 < khi; k0 += KT) {
-      const bool more = (k0 + KT < khi);
-      if (more) load(k0 + KT);
-      const u16* base = lds + buf * (S::NT * S::TILE);
+  auto stage_compute = [&](const u16* base) {
+    constexpr int KS = S::KT / 16;
+    if (NSPLIT == 1) {
+      u32x4 fa[2][4], fb[2][4];
 #pragma unroll
-      for (int ks = 0; ks < KT; ks += 16) {
-        u32x4 av[4], bv[4];
+      for (int b = 0; b < 4; ++b) {
+        fa[0][b] = frag(base, 0, 0, b);
+        fb[0][b] = frag(base, 1, 0, b);
+      }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          av[i] = *(const u32x4*)(base + (wm * 128 + i * 32 + (lane & 31)) * SK + ks + 8 * (lane >> 5));
+      for (int ks = 0; ks < KS; ++ks) {
+        const int c = ks & 1;
+        if (ks + 1 < KS) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          bv[j] = *(const u32x4*)(base + S::TILE + (wn * 128 + j * 32 + (lane & 31)) * SK + ks + 8 * (lane >> 5));
-        if (NSPLIT == 3) {
-          u32x4 al[4], bl[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            al[i] = *(const u32x4*)(base + 2 * S::TILE + (wm * 128 + i * 32 + (lane & 31)) * SK + ks + 8 * (lane >> 5));
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            bl[j] = *(const u32x4*)(base + 3 * S::TILE + (wn * 128 + j * 32 + (lane & 31)) * SK + ks + 8 * (lane >> 5));
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              acc[i][j] = mma<F16>(av[i], bl[j], acc[i][j]);
-              acc[i][j] = mma<F16>(al[i], bv[j], acc[i][j]);
-            }
+          for (int b = 0; b < 4; ++b) {
+            fa[c ^ 1][b] = frag(base, 0, 16 * (ks + 1), b);
+            fb[c ^ 1][b] = frag(base, 1, 16 * (ks + 1), b);
+          }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(av[i], bv[j], acc[i][j]);
+          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(fa[c][i], fb[c][j], acc[i][j]);
+        if (ks + 1 < KS) {  // interleave the next k step's 8 reads with these 16 MFMAs
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // MFMA
+          }
+        }
       }
-      if (more) store(buf ^ 1);
+    } else {
+      u32x4 ah[2][4], bh[2][4], al[2][4], bl[2][4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        ah[0][b] = frag(base, 0, 0, b);
+        bl[0][b] = frag(base, 3, 0, b);
+        al[0][b] = frag(base, 2, 0, b);
+        bh[0][b] = frag(base, 1, 0, b);
+      }
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int c = ks & 1;
+        if (ks + 1 < KS) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            ah[c ^ 1][b] = frag(base, 0, 16 * (ks + 1), b);
+            bl[c ^ 1][b] = frag(base, 3, 16 * (ks + 1), b);
+            al[c ^ 1][b] = frag(base, 2, 16 * (ks + 1), b);
+            bh[c ^ 1][b] = frag(base, 1, 16 * (ks + 1), b);
+          }
+        }
+        // dependent updates of one accumulator are 16 MFMAs apart
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(ah[c][i], bl[c][j], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(al[c][i], bh[c][j], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(ah[c][i], bh[c][j], acc[i][j]);
+        if (ks + 1 < KS) {  // 16 reads among 48 MFMAs
+#pragma unroll
+          for (int g = 0; g < 16; ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
+          }
+        }
+      }
+    }
+  };
+
+  if (klo < khi) {
+    issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = klo; k0 < khi; k0 += S::KT) {
+      const u16* base = lds + buf * (S::NT * S::TILE);
+      if (k0 + S::KT < khi) issue(buf ^ 1, k0 + S::KT - klo);
+      bool guard = (k0 + S::KT > K);
+      if (AM != 0 && k0 + S::KT > m0 && k0 < m0 + LT) guard = true;
+      if (BM != 0 && k0 + S::KT > n0 && k0 < n0 + LT) guard = true;
+      if (guard) {
+        mask_lds(buf, k0);
+        __syncthreads();
+      }
+      stage_compute(base);
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       buf ^= 1;
     }
@@ -397,7 +456,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
 template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
 static hipError_t go_lp(const LpGemmArgs& a, hipStream_t s, int64_t total) {
   typedef LpShape<NSPLIT> S;
-  const size_t lds = 2u * S::NT * S::TILE * sizeof(unsigned short);
+  const size_t lds = 2u * S::NT * S::TILE * sizeof(unsigned short);  // two stages
   auto k = k_gemm_lp<F16, NSPLIT, AM, BM, TILES, ORDER, KLO, KHI, EPI>;
   static bool attr_set = false;  // per instantiation
   if (!attr_set) {

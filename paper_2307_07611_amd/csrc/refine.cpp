@@ -48,7 +48,7 @@ struct WsRefine {
 WsRefine carve_refine(Carve& c, int64_t n, int64_t leaf) {
   WsRefine w;
   w.ldp = lp_ld(n);
-  const size_t pl = (size_t)n * w.ldp + 64;  // one low-precision plane (+ slack for over-reads)
+  const size_t pl = (size_t)n * w.ldp + 512;  // one low-precision plane (+ slack for over-reads)
   w.status = c.take<uint64_t>(1);
   w.Lhi = c.take<unsigned short>(pl);
   w.Llo = c.take<unsigned short>(pl);
@@ -56,7 +56,7 @@ WsRefine carve_refine(Carve& c, int64_t n, int64_t leaf) {
   w.Xbt = c.take<unsigned short>(pl);
   w.Xtlo = c.take<unsigned short>(pl);
   w.Rt = c.take<unsigned short>(pl);
-  w.Tt = c.take<unsigned short>((size_t)lp_t_elems(n, leaf) + 64);
+  w.Tt = c.take<unsigned short>((size_t)lp_t_elems(n, leaf) + 512);
   w.R32 = c.take<float>((size_t)n * n);
   w.dL = c.take<double>((size_t)n);
   w.dX = c.take<double>((size_t)n);
