@@ -129,10 +129,25 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   const GemmBatch bt = a.bt;
   const int64_t tm = (bt.M + LT - 1) / LT, tn = (bt.N + LT - 1) / LT;
   const int64_t nz = bt.nmerge;
-  const int64_t total = (TILES == kLowerTiles) ? nz * tm * (tm + 1) / 2 : nz * tm * tn;
-  const int64_t t = xcd_remap(blockIdx.x, total, 4);
-  int64_t z, it, jt;
-  decode_lp<TILES, ORDER>(t, nz, tm, tn, z, it, jt);
+  // L2-aware schedule: tiles are grouped in GB x GB blocks run by 16
+  // consecutive workgroups of one XCD (block B on XCD B % 8; workgroups are
+  // dispatched round-robin over the 8 XCDs), so a block's tiles share GB row
+  // panels and GB column panels in that XCD's L2. Blocks are taken heaviest
+  // first; there are enough of them to keep the XCDs balanced.
+  constexpr int GB = 4;
+  const int64_t bm = (tm + GB - 1) / GB, bn = (tn + GB - 1) / GB;
+  const int64_t nblk = (TILES == kLowerTiles) ? nz * bm * (bm + 1) / 2 : nz * bm * bn;
+  const int64_t w = blockIdx.x, x = w % kNumXcd, q = w / kNumXcd;
+  const int64_t B = (q / (GB * GB)) * kNumXcd + x;
+  const int pos = (int)(q % (GB * GB));
+  if (B >= nblk) return;
+  int64_t z, bi, bj;
+  decode_lp<TILES, ORDER>(B, nz, bm, bn, z, bi, bj);
+  const int64_t it = bi * GB + pos % GB, jt = bj * GB + pos / GB;
+  // slot of this tile in the per-tile partial sums (lower tiles packed)
+  const int64_t t = (TILES == kLowerTiles) ? z * tm * (tm + 1) / 2 + it * (it + 1) / 2 + jt : (z * tm + it) * tn + jt;
+  if (it >= tm || jt >= tn) return;
+  if (TILES == kLowerTiles && it < jt) return;
   const bool last = (z == bt.nmerge - 1);
   const int64_t M = last ? bt.M_last : bt.M, N = last ? bt.N_last : bt.N, K = last ? bt.K_last : bt.K;
   const int64_t m0 = it * LT, n0 = jt * LT;
@@ -453,6 +468,15 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   }
 }
 
+// Workgroups to launch: 16 per 4 x 4 tile block, blocks rounded up to a
+// multiple of the XCD count (the extra ones exit at once).
+static int64_t lp_grid(const GemmBatch& bt, int tiles) {
+  const int64_t tm = (bt.M + LT - 1) / LT, tn = (bt.N + LT - 1) / LT;
+  const int64_t bm = (tm + 3) / 4, bn = (tn + 3) / 4;
+  const int64_t nblk = tiles == kLowerTiles ? bt.nmerge * bm * (bm + 1) / 2 : bt.nmerge * bm * bn;
+  return (nblk + kNumXcd - 1) / kNumXcd * kNumXcd * 16;
+}
+
 template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
 static hipError_t go_lp(const LpGemmArgs& a, hipStream_t s, int64_t total) {
   typedef LpShape<NSPLIT> S;
@@ -495,7 +519,7 @@ static hipError_t dispatch_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_
 
 hipError_t launch_gemm_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_t s) {
   if (a.bt.nbatch != 1) return hipErrorInvalidValue;
-  const int64_t total = gemm_lp_tiles(a.bt, c.tiles);
+  const int64_t total = lp_grid(a.bt, c.tiles);
   if (total <= 0) return hipSuccess;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
   if (c.tiles == kLowerTiles && a.bt.M != a.bt.N) return hipErrorInvalidValue;
