@@ -27,8 +27,18 @@ sys.path.insert(0, ROOT)
 METRIC = "TFLOP/s (n^3/3) tril inverse n=16384: BF16+refine vs FP64, equal residual"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}
 HBM_PEAK_GBS = 8000.0
-CLASS_DTYPE = {"gemm_f64": "f64", "gemm_f32": "f32", "gemm_bf16": "bf16", "gemm_f16": "f16",
-               "leaf_f64": "f64", "leaf_f32": "f32"}
+# Library profile classes that are matrix-core products (one class = one kernel
+# instantiation); the leading token is the operand precision.
+MFMA_KINDS = ("level_T", "level_X21", "residual", "correction")
+# HBM traffic per launch measured with hardware counters, keyed by profile class
+# and by a hash of the kernel sources at the time of the measurement.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n16384.md")
+KERNEL_SOURCES = {
+    "bf16": ["paper_2307_07611_amd/csrc/gemm_lp.hip", "paper_2307_07611_amd/csrc/lowp.h",
+             "paper_2307_07611_amd/csrc/common.h"],
+    "f64": ["paper_2307_07611_amd/csrc/gemm_fp.hip", "paper_2307_07611_amd/csrc/launch.h",
+            "paper_2307_07611_amd/csrc/common.h"],
+}
 
 
 def log(msg):
@@ -62,18 +72,63 @@ def time_path(P, torch, Ld, mode, steps, warmup, leaf):
     return X, ms, wall, prof, infos[-1]
 
 
-def roofline(prof):
-    gemm = {k: v for k, v in prof.items() if k.startswith("gemm")}
-    if not gemm:
+def sources_hash(dtype):
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES.get(dtype, []):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cls, dtype):
+    """HBM bytes per launch of `cls` from the committed counter summary, or None
+    when there is none or the kernel sources changed since it was taken.
+    Table rows: | class | sources hash | fetch bytes | write bytes | total bytes |"""
+    if not os.path.exists(TRAFFIC_FILE):
         return None
-    name, e = max(gemm.items(), key=lambda kv: kv[1]["total_ms"])
+    want = sources_hash(dtype)
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 5 and cells[0] == cls and cells[1] == want:
+                try:
+                    return float(cells[4])
+                except ValueError:
+                    return None
+    return None
+
+
+def roofline(prof):
+    mm = {k: v for k, v in prof.items() if k.split("_", 1)[-1] in MFMA_KINDS and v["launches"]}
+    if not mm:
+        return None
+    name, e = max(mm.items(), key=lambda kv: kv[1]["total_ms"])
+    dtype = name.split("_", 1)[0]
     avg_ms = e["total_ms"] / e["launches"]
     achieved = (e["flops"] / e["launches"]) / (avg_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[CLASS_DTYPE[name]]
-    return {"bound": "mfma", "kernel_class": name, "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-            "launches": e["launches"], "avg_launch_ms": round(avg_ms, 4),
-            "flops_per_launch": e["flops"] / e["launches"]}
+    peak = PEAK_TFLOPS[dtype]
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": measured_traffic(name, dtype),
+            "kernel_class": name, "launches": e["launches"], "avg_launch_ms": round(avg_ms, 4),
+            "flops_per_launch": e["flops"] / e["launches"], "sources_hash": sources_hash(dtype)}
+
+
+def copy_calibration(mib, reps):
+    """Plain copy kernel of known size (elementwise negate, fp32) to scale the
+    hardware byte counters: each launch reads and writes exactly `mib` MiB."""
+    import torch
+
+    src = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "launches": reps,
+                      "bytes_read_per_launch": src.numel() * 4, "bytes_written_per_launch": dst.numel() * 4}),
+          flush=True)
 
 
 def cpu_baseline(L, seconds):
@@ -115,11 +170,17 @@ def main():
     ap.add_argument("--paths", default="bf16_refine,f64")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain copy kernel of this size (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the multi-GPU sharding is a design note, not code)"}), flush=True)
         sys.exit(2)
+
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib, max(args.steps, 1))
+        return
 
     import torch
 

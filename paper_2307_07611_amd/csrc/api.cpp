@@ -84,10 +84,12 @@ hipError_t run_levels(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int
     const double fl2 = ((double)full * fh * fh * (fh + 1) + (double)batch * fh * hB * (hB + 1));
     const double by1 = es * ((double)full * (fh * fh + fh * fh / 2 + fh * fh) + (double)batch * (hB * fh + fh * fh / 2 + hB * fh));
     const double by2 = es * ((double)full * (fh * fh / 2 + fh * fh + 2 * fh * fh) + (double)batch * (hB * hB / 2 + hB * fh + 2 * hB * fh));
-    const char* cls = sizeof(T) == 8 ? "gemm_f64" : "gemm_f32";
+    // one profile class per kernel instantiation
+    const char* cls1 = sizeof(T) == 8 ? "f64_level_T" : "f32_level_T";
+    const char* cls2 = sizeof(T) == 8 ? "f64_level_X21" : "f32_level_X21";
     hipError_t e;
     {
-      ProfLaunch pl(cls, fl1, by1, s);
+      ProfLaunch pl(cls1, fl1, by1, s);
       e = launch_gemm<T, TC>(g1, s);
     }
     if (e != hipSuccess) return e;
@@ -103,7 +105,7 @@ hipError_t run_levels(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int
     g2.khi = kHiM1;
     g2.bt = {lv.nmerge, batch, hA, hA, hA, lv.hB_last, hA, lv.hB_last};
     {
-      ProfLaunch pl(cls, fl2, by2, s);
+      ProfLaunch pl(cls2, fl2, by2, s);
       e = launch_gemm<T, TC>(g2, s);
     }
     if (e != hipSuccess) return e;

@@ -92,7 +92,7 @@ hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, c
     LpConfig c1{f16, 1, 0, 1, kAllTiles, kColAsc, kLoN0, kHiK, kLpEpT};
     hipError_t e;
     {
-      ProfLaunch pl(f16 ? "gemm_f16" : "gemm_bf16", full * fh * fh * (fh + 1) + hB * fh * (fh + 1),
+      ProfLaunch pl(f16 ? "f16_level_T" : "bf16_level_T", full * fh * fh * (fh + 1) + hB * fh * (fh + 1),
                     2.0 * (full * 2.5 * fh * fh + (2 * hB * fh + fh * fh / 2)), s);
       e = launch_gemm_lp(g1, c1, s);
     }
@@ -119,7 +119,7 @@ hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, c
     g2.xlpt_bstride = stp;
     LpConfig c2{f16, 1, 1, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kLpEpX21};
     {
-      ProfLaunch pl(f16 ? "gemm_f16" : "gemm_bf16", full * fh * fh * (fh + 1) + fh * hB * (hB + 1),
+      ProfLaunch pl(f16 ? "f16_level_X21" : "bf16_level_X21", full * fh * fh * (fh + 1) + fh * hB * (hB + 1),
                     full * (2 * (fh * fh / 2 + fh * fh) + 12 * fh * fh) + (2 * (hB * hB / 2 + hB * fh) + 12 * hB * fh),
                     s);
       e = launch_gemm_lp(g2, c2, s);
@@ -226,7 +226,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       gf.tile_sq = w.tile_sq;
       gf.tile_sqx = w.tile_sqx;
       {
-        ProfLaunch pl("gemm_f64", tri_flops(dn), dn * dn / 2 * (8 * 2 + 8 + 8 + 4 + 2), s);
+        ProfLaunch pl("f64_residual", tri_flops(dn), dn * dn / 2 * (8 * 2 + 8 + 8 + 4 + 2), s);
         HIP_TRY(launch_gemm<double, double>(gf, s));
       }
       const int64_t ntf = gemm_tiles(bt, kLowerTiles);
@@ -256,7 +256,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gr.tile_sqx = w.tile_sqx;
     LpConfig cr{f16, 3, 2, 2, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpResid};
     {
-      ProfLaunch pl(f16 ? "gemm_f16" : "gemm_bf16", 3.0 * tri_flops(dn), dn * dn / 2 * (4 * 2 + 8 + 8 + 4 + 2), s);
+      ProfLaunch pl(f16 ? "f16_residual" : "bf16_residual", 3.0 * tri_flops(dn), dn * dn / 2 * (4 * 2 + 8 + 8 + 4 + 2), s);
       HIP_TRY(launch_gemm_lp(gr, cr, s));
     }
     const int64_t ntl = gemm_lp_tiles(bt, kLowerTiles);
@@ -300,7 +300,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gc.ldr = n;
     LpConfig cc{f16, 1, 2, 1, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpCorr};
     {
-      ProfLaunch pl(f16 ? "gemm_f16" : "gemm_bf16", tri_flops(dn) + dn * dn, dn * dn / 2 * (2 + 2 + 4 + 16), s);
+      ProfLaunch pl(f16 ? "f16_correction" : "bf16_correction", tri_flops(dn) + dn * dn, dn * dn / 2 * (2 + 2 + 4 + 16), s);
       HIP_TRY(launch_gemm_lp(gc, cc, s));
     }
     ++iter;
