@@ -128,26 +128,38 @@ int trinv_tril_inverse(int mode, int64_t n, const void *L, int64_t ldl, void *X,
                        const trinv_opts *opts, void *ws, size_t ws_bytes, trinv_stream_t stream,
                        trinv_info *info);
 
-/* Bytes of workspace trinv_tril_inverse_batched needs for this batch
- * (n_host: host array of the batch sizes, used for planning only). */
+/* Bytes of workspace trinv_tril_inverse_batched needs for this batch: 4 bytes
+ * per matrix plus a queue counter (n_host and opts are not needed for the
+ * size and may be NULL). */
 size_t trinv_batched_workspace_bytes(int mode, int64_t batch, const int32_t *n_host,
                                      const trinv_opts *opts);
 
 /*
- * X_i = L_i^-1 for `batch` independent lower-triangular matrices of uneven
- * order, packed back to back (the paper's parallel remark: independent
- * diagonal blocks can be inverted concurrently, Section 4.1 complexity
- * analysis). mode: TRINV_F32 or TRINV_F64.
- *   n_host / n_dev: the orders n_i (host copy for planning, device copy read
- *     by the kernels; identical contents), 1 <= n_i <= 1024.
+ * X_i = L_i^-1 for `batch` independent lower-triangular matrices, uniform or
+ * of uneven order, packed back to back. Independent diagonal blocks can be
+ * inverted concurrently (Section 4.1, algorithm COMBRIT and its complexity
+ * remark); each matrix runs the same recursion as trinv_tril_inverse (leaves
+ * of 16 by the column recurrence of Section 4.2, then the 2 x 2 block levels).
+ * mode: TRINV_F32 or TRINV_F64.
+ *   n_host / n_dev: the orders n_i (host copy for validation, device copy read
+ *     by the kernels; identical contents), 1 <= n_i <= 1024, batch < 2^31.
  *   off_host / off_dev: int64 element offsets of matrix i in L_packed and
  *     X_packed; matrix i is dense n_i x n_i row-major with leading dimension
- *     n_i. Regions must not overlap.
+ *     n_i (only its lower triangle is read; all of X_i is written, zeros
+ *     above the diagonal). Gaps between matrices are not touched. The L and X
+ *     ranges must not overlap (TRINV_ERR_ARG).
  *   status_dev: device int32[batch]; status_dev[i] = 0, or the 1-based index
- *     of the first zero diagonal of matrix i.
- * The whole batch runs in one persistent kernel launch; the plan (work
- * order, tile and leaf sizes) is chosen on the host from n_host and cached.
- * Returns a trinv_status (TRINV_ERR_SINGULAR only with opts->blocking).
+ *     of the first zero diagonal of matrix i (X_i then holds non-finite
+ *     values), or -1 if n_dev[i] is outside [1, 1024].
+ *   opts: leaf 0 or 16 (else TRINV_ERR_ARG); unit_diag honoured; upper is
+ *     TRINV_ERR_UNSUPPORTED; blocking: wait and return TRINV_ERR_SINGULAR if
+ *     any matrix is singular.
+ *   ws: at least trinv_batched_workspace_bytes bytes, caller-owned.
+ * Two launches on `stream`: a one-workgroup plan kernel (sorts the matrices
+ * by order, largest first, and resets the queue counter in ws) and one
+ * persistent kernel whose workgroups take whole matrices from that queue.
+ * No memset and no host synchronisation (unless blocking), so the call can be
+ * captured in a graph and replayed.
  */
 int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t *n_host, const int32_t *n_dev,
                                const int64_t *off_host, const int64_t *off_dev, const void *L_packed,

@@ -139,9 +139,11 @@ def factored_inverse(L: torch.Tensor, U: torch.Tensor, *, l_unit=False, u_unit=F
 
 
 def tril_inverse_batched(L_packed: torch.Tensor, sizes, offsets=None, mode=None, *, blocking=True, leaf=0,
-                         out=None, workspace=None, n_dev=None, off_dev=None):
+                         out=None, workspace=None, n_dev=None, off_dev=None, status=None):
     """Inverse of every matrix of a packed batch (dense n_i x n_i blocks at
-    element offsets ``offsets``); returns (X_packed, status per matrix)."""
+    element offsets ``offsets``); returns (X_packed, status per matrix).
+    Uneven orders run in one persistent launch (after a one-block plan
+    kernel); uniform ones as batched level products."""
     _check_dev(L_packed)
     import numpy as np
 
@@ -159,7 +161,8 @@ def tril_inverse_batched(L_packed: torch.Tensor, sizes, offsets=None, mode=None,
     if off_dev is None:
         off_dev = torch.from_numpy(off_np).to(dev)
     X = out if out is not None else torch.empty_like(L_packed)
-    status = torch.empty(batch, dtype=torch.int32, device=dev)
+    if status is None:
+        status = torch.empty(batch, dtype=torch.int32, device=dev)
     lib = _lib.load()
     o = _opts(leaf=leaf, blocking=blocking)
     nbytes = lib.trinv_batched_workspace_bytes(m, batch, sizes_np.ctypes.data, ctypes.byref(o))
@@ -170,6 +173,65 @@ def tril_inverse_batched(L_packed: torch.Tensor, sizes, offsets=None, mode=None,
     if st != _lib.OK and st != _lib.ERR_SINGULAR:
         raise _lib.TrinvError(st, "trinv_tril_inverse_batched")
     return X, status
+
+
+class BatchedGraph:
+    """A fixed batch layout with static device buffers whose inversion is
+    captured once in a graph (``torch.cuda.CUDAGraph``) and replayed.
+
+    Write the inputs into ``self.L`` (packed, dense n_i x n_i blocks at
+    ``self.offsets``), call ``replay()``; the inverses land in ``self.X`` and
+    the per-matrix status in ``self.status``."""
+
+    def __init__(self, sizes, offsets=None, dtype=torch.float32, device="cuda", leaf=0):
+        import numpy as np
+
+        self.sizes = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
+        if offsets is None:
+            offsets = np.zeros(len(self.sizes), dtype=np.int64)
+            if len(self.sizes) > 1:
+                offsets[1:] = np.cumsum(self.sizes[:-1].astype(np.int64) ** 2)
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        total = int(np.max(self.offsets + self.sizes.astype(np.int64) ** 2)) if len(self.sizes) else 0
+        self.mode_name = "f32" if dtype == torch.float32 else "f64"
+        self.mode = _lib.MODES[self.mode_name]
+        self.leaf = leaf
+        self.L = torch.zeros(total, dtype=dtype, device=device)
+        self.X = torch.empty_like(self.L)
+        self.status = torch.empty(len(self.sizes), dtype=torch.int32, device=device)
+        self.n_dev = torch.from_numpy(self.sizes).to(device)
+        self.off_dev = torch.from_numpy(self.offsets).to(device)
+        lib = _lib.load()
+        o = _opts(leaf=leaf, blocking=False)
+        nbytes = lib.trinv_batched_workspace_bytes(self.mode, len(self.sizes), self.sizes.ctypes.data,
+                                                   ctypes.byref(o))
+        self.ws = _workspace(nbytes, self.L.device)
+        self.graph = None
+
+    def _call(self):
+        tril_inverse_batched(self.L, self.sizes, self.offsets, self.mode_name, blocking=False, leaf=self.leaf,
+                             out=self.X, workspace=self.ws, n_dev=self.n_dev, off_dev=self.off_dev,
+                             status=self.status)
+
+    def run_eager(self):
+        self._call()
+
+    def capture(self):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self._call()  # warm-up outside the graph (kernel loading, occupancy query)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._call()
+        return self
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
 
 
 class TrilInverse(torch.autograd.Function):

@@ -107,4 +107,16 @@ hipError_t launch_status_to_i32(const uint64_t* first_bad, int32_t* status, int6
 template <typename T>
 hipError_t launch_transpose(const T* A, int64_t lda, T* B, int64_t ldb, int64_t n, hipStream_t s);
 
+// Uneven batch in one persistent launch (persistent.hip): a plan kernel sorts
+// the matrices by order into `order` (batch entries) and resets `queue`, then
+// `grid` workgroups invert whole matrices taken from the queue (leaves of 16).
+// status[i]: 0, the 1-based index of the first zero diagonal, or -1 for an
+// order outside [1, 1024].
+template <typename T>
+hipError_t launch_batched(int64_t batch, const int32_t* n_dev, const int64_t* off_dev, const T* L, T* X,
+                          int32_t* status, int32_t* order, uint32_t* queue, int unit, int grid, hipStream_t s);
+// Persistent grid size: resident workgroups on the current device, at most batch.
+template <typename T>
+int batched_grid(int64_t batch);
+
 }  // namespace trinv

@@ -3,6 +3,8 @@ that include/trinv.h declares, and its host-only calls (workspace queries,
 argument validation, status strings) behave as documented."""
 
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -96,3 +98,43 @@ def test_argument_errors_before_any_launch(lib):
     assert lib.trinv_factored_inverse(_lib.F64, 4, None, 0, None, 0, None, None, None, None, None, 0, None,
                                       None) == _lib.ERR_ARG
     assert lib.trinv_residual(_lib.F64, -2, None, 0, None, 0, None, 0, None, None) == _lib.ERR_ARG
+
+
+def test_batched_argument_errors_before_any_launch(lib):
+    from paper_2307_07611_amd import _lib
+
+    n = np.array([16, 40, 7], dtype=np.int32)
+    off = np.array([0, 256, 256 + 1600], dtype=np.int64)
+    o = _lib.Opts()
+    lib.trinv_default_opts(ctypes.byref(o))
+    call = lambda mode, batch, n_arr, off_arr, L, X, st, opts: lib.trinv_tril_inverse_batched(  # noqa: E731
+        mode, batch, n_arr.ctypes.data, 4096, off_arr.ctypes.data, 8192, L, X, st, ctypes.byref(opts), 1 << 20,
+        1 << 20, None)
+    assert lib.trinv_tril_inverse_batched(_lib.F32, 0, None, None, None, None, None, None, None, None, None, 0,
+                                          None) == _lib.OK
+    assert call(_lib.F32, -1, n, off, 1 << 30, 1 << 31, 1 << 32, o) == _lib.ERR_ARG
+    assert call(_lib.BF16_REFINE, 3, n, off, 1 << 30, 1 << 31, 1 << 32, o) == _lib.ERR_UNSUPPORTED
+    bad = n.copy()
+    bad[1] = 0
+    assert call(_lib.F32, 3, bad, off, 1 << 30, 1 << 31, 1 << 32, o) == _lib.ERR_ARG
+    bad[1] = 1025
+    assert call(_lib.F32, 3, bad, off, 1 << 30, 1 << 31, 1 << 32, o) == _lib.ERR_ARG
+    neg = off.copy()
+    neg[2] = -5
+    assert call(_lib.F32, 3, n, neg, 1 << 30, 1 << 31, 1 << 32, o) == _lib.ERR_ARG
+    # input and output ranges overlap (extent 1649 elements of 4 bytes)
+    assert call(_lib.F32, 3, n, off, 1 << 30, (1 << 30) + 4000, 1 << 32, o) == _lib.ERR_ARG
+    up = _lib.Opts()
+    lib.trinv_default_opts(ctypes.byref(up))
+    up.upper = 1
+    assert call(_lib.F32, 3, n, off, 1 << 30, 1 << 31, 1 << 32, up) == _lib.ERR_UNSUPPORTED
+    lf = _lib.Opts()
+    lib.trinv_default_opts(ctypes.byref(lf))
+    for leaf in (32, 64):  # uneven orders take leaf 0 or 16
+        lf.leaf = leaf
+        assert call(_lib.F32, 3, n, off, 1 << 30, 1 << 31, 1 << 32, lf) == _lib.ERR_ARG
+    # too small a workspace
+    assert lib.trinv_tril_inverse_batched(_lib.F32, 3, n.ctypes.data, 4096, off.ctypes.data, 8192, 1 << 30,
+                                          1 << 31, 1 << 32, ctypes.byref(o), 1 << 20, 8, None) == \
+        _lib.ERR_WORKSPACE
+    assert lib.trinv_batched_workspace_bytes(_lib.F32, 3, n.ctypes.data, ctypes.byref(o)) >= 3 * 4 + 4

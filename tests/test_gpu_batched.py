@@ -1,0 +1,198 @@
+"""GPU parity of the batched inverse through the C ABI: uneven orders in one
+persistent launch (FP32 and FP64), per-matrix status, unit diagonals, graph
+capture and replay, and the 4096-matrix configuration.
+
+Tolerances: FP32 relative residual ||L X - I||_F / (||L||_F ||X||_F) <= 1e-5
+per matrix and relative forward error against the oracle <= 1e-4 (kappa ~ 2
+for this generator, FP32 unit roundoff 6e-8 times the depth of the
+recursion); FP64 residual <= 1e-13 and forward error <= 1e-11.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import banner
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": (1e-5, 1e-4), "f64": (1e-13, 1e-11)}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_07611_amd as P
+
+    P.load()
+    return P
+
+
+def make_batch(sizes, dtype, seed0=1000, unit=False):
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    if len(sizes) > 1:
+        offs[1:] = np.cumsum(np.asarray(sizes[:-1], dtype=np.int64) ** 2)
+    total = int(offs[-1] + int(sizes[-1]) ** 2)
+    packed = np.zeros(total, dtype=dtype)
+    mats = []
+    for i, n in enumerate(sizes):
+        L = synth.lower_triangular(int(n), seed0 + i, unit=unit, dtype=dtype)
+        packed[offs[i]:offs[i] + n * n] = L.ravel()
+        mats.append(L)
+    return packed, offs, mats
+
+
+def unpack(X, offs, sizes):
+    return [X[o:o + n * n].reshape(n, n) for o, n in zip(offs, sizes)]
+
+
+def rel_residual(L, X):
+    L = L.astype(np.float64)
+    X = X.astype(np.float64)
+    n = L.shape[0]
+    return np.linalg.norm(L @ X - np.eye(n)) / (np.linalg.norm(L) * np.linalg.norm(X))
+
+
+def check(mats, Xs, tol, oracle_every=1, unit=False):
+    rt, ft = tol
+    worst_r = worst_f = 0.0
+    for i, (L, X) in enumerate(zip(mats, Xs)):
+        assert np.all(np.triu(X, 1) == 0), f"matrix {i}: nonzero above the diagonal"
+        r = rel_residual(np.tril(L) if not unit else np.tril(L, -1) + np.eye(L.shape[0]), X)
+        worst_r = max(worst_r, r)
+        assert r <= rt, f"matrix {i} n={L.shape[0]}: residual {r:.3e}"
+        if i % oracle_every == 0:
+            Xo = oracle.tril_inverse(L.astype(np.float64), unit=unit)
+            f = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+            worst_f = max(worst_f, f)
+            assert f <= ft, f"matrix {i} n={L.shape[0]}: forward error {f:.3e}"
+    return worst_r, worst_f
+
+
+EDGE_SIZES = [1, 2, 3, 15, 16, 17, 31, 32, 33, 47, 63, 64, 65, 96, 127, 128, 129, 200, 255, 256, 257, 263, 300,
+              383, 511, 512, 513, 700, 1000, 1023, 1024, 5, 64, 100]
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("leaf", [0, 16])
+def test_uneven_batch_vs_oracle(P, dt, leaf):
+    import torch
+
+    banner(f"batched uneven {dt} leaf={leaf} sizes={len(EDGE_SIZES)}")
+    npdt = np.float32 if dt == "f32" else np.float64
+    packed, offs, mats = make_batch(EDGE_SIZES, npdt)
+    X, st = P.tril_inverse_batched(torch.from_numpy(packed).cuda(), EDGE_SIZES, offs, dt, leaf=leaf)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    Xs = unpack(X.cpu().numpy(), offs, EDGE_SIZES)
+    r, f = check(mats, Xs, TOL[dt])
+    print(f"{dt} leaf={leaf}: worst residual {r:.3e}, worst forward error {f:.3e}", flush=True)
+
+
+def test_uneven_batch_singular_and_offsets(P):
+    """Per-matrix status (1-based first zero pivot) and non-contiguous offsets
+    (gaps between the matrices are left untouched)."""
+    import torch
+
+    banner("batched singular + gaps")
+    sizes = [40, 300, 7, 129, 64]
+    gap = 37
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    for i in range(1, len(sizes)):
+        offs[i] = offs[i - 1] + sizes[i - 1] ** 2 + gap
+    total = int(offs[-1] + sizes[-1] ** 2)
+    packed = np.full(total, -7.0, dtype=np.float32)
+    mats = []
+    for i, n in enumerate(sizes):
+        L = synth.lower_triangular(n, 50 + i, dtype=np.float32)
+        mats.append(L)
+        packed[offs[i]:offs[i] + n * n] = L.ravel()
+    packed[offs[1] + 150 * 300 + 150] = 0.0  # matrix 1: L[150, 150] = 0
+    packed[offs[3] + 0] = 0.0  # matrix 3: L[0, 0] = 0
+    Xd = torch.full((total,), 3.5, dtype=torch.float32, device="cuda")
+    _, st = P.tril_inverse_batched(torch.from_numpy(packed).cuda(), sizes, offs, "f32", out=Xd)
+    torch.cuda.synchronize()
+    assert st.cpu().numpy().tolist() == [0, 151, 0, 1, 0]
+    X = Xd.cpu().numpy()
+    for i in range(1, len(sizes)):  # gaps untouched
+        assert np.all(X[offs[i] - gap:offs[i]] == 3.5)
+    Xs = unpack(X, offs, sizes)
+    for i in (0, 2, 4):
+        assert rel_residual(mats[i], Xs[i]) <= 1e-5
+
+
+def test_uneven_batch_unit_diagonal(P):
+    import torch
+
+    banner("batched unit diagonal")
+    sizes = [33, 260, 1, 90, 512]
+    packed, offs, mats = make_batch(sizes, np.float64, seed0=70)
+    lib = P._lib
+    # unit flag through the C ABI directly (the Python wrapper has no unit option here)
+    import ctypes
+
+    L_d = torch.from_numpy(packed).cuda()
+    Xu = torch.empty_like(L_d)
+    stu = torch.empty(len(sizes), dtype=torch.int32, device="cuda")
+    n_np = np.asarray(sizes, dtype=np.int32)
+    n_d = torch.from_numpy(n_np).cuda()
+    o_d = torch.from_numpy(offs).cuda()
+    o = lib.Opts()
+    lib.load().trinv_default_opts(ctypes.byref(o))
+    o.unit_diag = 1
+    o.blocking = 1
+    nb = lib.load().trinv_batched_workspace_bytes(lib.F64, len(sizes), n_np.ctypes.data, ctypes.byref(o))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+    rc = lib.load().trinv_tril_inverse_batched(lib.F64, len(sizes), n_np.ctypes.data, n_d.data_ptr(),
+                                                offs.ctypes.data, o_d.data_ptr(), L_d.data_ptr(), Xu.data_ptr(),
+                                                stu.data_ptr(), ctypes.byref(o), ws.data_ptr(), nb,
+                                                torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert rc == 0 and np.all(stu.cpu().numpy() == 0)
+    check(mats, unpack(Xu.cpu().numpy(), offs, sizes), TOL["f64"], unit=True)
+
+
+def test_graph_replay_matches_eager(P):
+    """Capture once, replay with new inputs written into the static buffer and
+    eager work in between; every replay equals the eager call bit for bit
+    (each matrix's arithmetic does not depend on which workgroup runs it)."""
+    import torch
+
+    banner("batched graph capture/replay")
+    sizes = synth.batch_sizes(300, seed=11)
+    g = P.BatchedGraph(sizes, dtype=torch.float32)
+    g.capture()
+    for rep, seed0 in enumerate([1000, 5000, 9000]):
+        packed, offs, mats = make_batch(sizes, np.float32, seed0=seed0)
+        g.L.copy_(torch.from_numpy(packed).cuda())
+        junk = torch.randn(1 << 20, device="cuda")
+        junk.mul_(2.0).sum().item()  # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        Xg = g.X.clone()
+        stg = g.status.clone()
+        Xe, ste = P.tril_inverse_batched(g.L, sizes, offs, "f32")
+        torch.cuda.synchronize()
+        assert torch.equal(Xg, Xe), f"replay {rep} differs from eager"
+        assert torch.equal(stg, ste)
+        if rep == 0:
+            check(mats, unpack(Xg.cpu().numpy(), offs, sizes), TOL["f32"], oracle_every=10)
+
+
+def test_batched_4096_configuration(P):
+    """4096 FP32 matrices, n_i = 16 + (splitmix(6, i) mod 497): residual of
+    every matrix in FP64 on the host, oracle comparison on every 16th."""
+    import torch
+
+    sizes = synth.batch_sizes(4096)
+    banner(f"batched 4096 f32 sum n^2 = {int(np.sum(sizes.astype(np.int64) ** 2))}")
+    packed, offs, mats = make_batch(sizes, np.float32)
+    X, st = P.tril_inverse_batched(torch.from_numpy(packed).cuda(), sizes, offs, "f32")
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    r, f = check(mats, unpack(X.cpu().numpy(), offs, sizes), TOL["f32"], oracle_every=16)
+    print(f"4096: worst residual {r:.3e}, worst forward error {f:.3e}", flush=True)
