@@ -131,6 +131,70 @@ def copy_calibration(mib, reps):
           flush=True)
 
 
+def time_events(torch, fn, reps):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batched_secondary(P, torch, reps):
+    """4096 FP32 matrices of order n_i = 16 + (splitmix(6, i) mod 497) in one
+    persistent launch, captured in a graph and replayed."""
+    import synth
+
+    sizes = synth.batch_sizes(4096)
+    g = P.BatchedGraph(sizes, dtype=torch.float32)
+    host = np.zeros(g.L.numel(), dtype=np.float32)
+    for i, n in enumerate(sizes):
+        o = int(g.offsets[i])
+        host[o:o + n * n] = synth.lower_triangular(int(n), 1000 + i, dtype=np.float32).ravel()
+    g.L.copy_(torch.from_numpy(host).cuda())
+    g.capture()
+    for _ in range(3):
+        g.replay()
+    ms = time_events(torch, g.replay, reps)
+    nn = sizes.astype(np.float64)
+    flops = float(np.sum(nn ** 3) / 3)
+    byts = float(np.sum(4 * (nn * (nn + 1) / 2 + nn * nn)))  # lower triangle in, full X out
+    st = g.status.cpu().numpy()
+    return {"workload": "batched: 4096 FP32 lower-triangular matrices, n_i = 16 + (splitmix64(6, i) mod 497), "
+                        "one persistent launch (graph replay)",
+            "ms": round(ms, 4), "tflops": round(flops / ms / 1e9, 3), "hbm_GBs": round(byts / ms / 1e6, 1),
+            "frac_fp32_mfma": round(flops / ms / 1e9 / PEAK_TFLOPS["f32"], 4),
+            "frac_hbm": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4), "sum_n3_over_3": flops,
+            "algorithmic_bytes": byts, "all_status_ok": bool(np.all(st == 0)), "reps": reps}
+
+
+def backward_secondary(P, torch, reps):
+    """64 FP32 matrices of order 1024: forward (batched path) and the adjoint
+    gradL = -tril(X^T G X^T) (two MFMA products per matrix)."""
+    import synth
+
+    batch, n = 64, 1024
+    L = torch.from_numpy(np.stack([synth.lower_triangular(n, 2000 + b, dtype=np.float32)
+                                   for b in range(batch)])).cuda()
+    G = torch.from_numpy(np.stack([synth.normal(n, n, 3000 + b, dtype=np.float32) for b in range(batch)])).cuda()
+    X = P.batched_uniform_inverse(L)
+    fwd = lambda: P.batched_uniform_inverse(L)  # noqa: E731
+    bwd = lambda: P.tril_inverse_backward(X, G)  # noqa: E731
+    for _ in range(2):
+        fwd()
+        bwd()
+    ms_f = time_events(torch, fwd, reps)
+    ms_b = time_events(torch, bwd, reps)
+    ff = batch * n ** 3 / 3.0
+    fb = batch * 2.0 * n ** 3 / 3.0
+    return {"workload": "backward: 64 FP32 lower-triangular matrices of order 1024, forward + adjoint",
+            "forward_ms": round(ms_f, 4), "forward_tflops": round(ff / ms_f / 1e9, 3),
+            "backward_ms": round(ms_b, 4), "backward_tflops": round(fb / ms_b / 1e9, 3),
+            "backward_frac_fp32_mfma": round(fb / ms_b / 1e9 / PEAK_TFLOPS["f32"], 4), "reps": reps}
+
+
 def cpu_baseline(L, seconds):
     """The oracle (column recurrence, all host cores via OpenMP) on a bounded
     sample of the same matrix: evenly spaced columns of L^-1."""
@@ -170,6 +234,8 @@ def main():
     ap.add_argument("--paths", default="bf16_refine,f64")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the batched and backward measurements")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain copy kernel of this size (counter calibration) and exit")
     args = ap.parse_args()
@@ -237,6 +303,13 @@ def main():
     }
     if "bf16_refine" in results and "f64" in results:
         out["speedup_vs_f64_path"] = round(results["f64"]["ms"] / results["bf16_refine"]["ms"], 3)
+    if not args.no_secondary:
+        log("batched 4096 FP32 (graph replay)")
+        out["secondary"] = {"batched": batched_secondary(P, torch, 20)}
+        log(f"batched: {out['secondary']['batched']['ms']} ms")
+        log("backward 64 x 1024 FP32")
+        out["secondary"]["backward"] = backward_secondary(P, torch, 10)
+        log(f"backward: {out['secondary']['backward']['backward_ms']} ms")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(L, args.cpu_seconds)

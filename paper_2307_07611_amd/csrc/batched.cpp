@@ -1,8 +1,9 @@
 // Batched inversion of many independent lower-triangular matrices of order
 // 1..1024: a one-workgroup plan kernel sorts the matrices by order, then one
 // persistent launch (persistent.hip) inverts them, each workgroup taking whole
-// matrices from a device-side queue. Uniform and uneven batches take the same
-// path.
+// matrices from a device-side queue. A uniform batch with fewer matrices than
+// compute units instead runs the level recursion with the batch as an extra
+// launch dimension (every level product spread over the whole chip).
 #include <algorithm>
 #include <vector>
 
@@ -25,16 +26,45 @@ WsPersistent carve_persistent(Carve& c, int64_t batch) {
   return w;
 }
 
+// Few equal orders packed densely: the level path fills the chip better.
+constexpr int64_t kLevelPathMaxBatch = 256;
+
+bool level_path(int64_t batch, const int32_t* n_host, const int64_t* off_host) {
+  if (batch > kLevelPathMaxBatch || n_host[0] < 128) return false;
+  for (int64_t i = 0; i < batch; ++i)
+    if (n_host[i] != n_host[0] || off_host[i] != i * (int64_t)n_host[0] * n_host[0]) return false;
+  return true;
+}
+
+struct WsLevels {
+  uint64_t* first_bad;
+  void* T;
+};
+
+WsLevels carve_levels(Carve& c, int mode, int64_t batch, int64_t n, int64_t leaf) {
+  WsLevels w;
+  const size_t es = mode == TRINV_F32 ? 4 : 8;
+  w.first_bad = c.take<uint64_t>((size_t)batch);
+  w.T = c.take<char>(es * (size_t)batch * (size_t)t_elems(n, leaf));
+  return w;
+}
+
+int64_t level_leaf(int mode, int64_t n, int32_t opt_leaf) { return opt_leaf ? opt_leaf : default_leaf(mode, n); }
+
 }  // namespace
 
 extern "C" size_t trinv_batched_workspace_bytes(int mode, int64_t batch, const int32_t* n_host,
                                                 const trinv_opts* opts) {
-  (void)mode;
-  (void)n_host;
-  (void)opts;
   if (batch <= 0) return 0;
   Carve c(nullptr, 0);
   carve_persistent(c, batch);
+  if (n_host && batch <= kLevelPathMaxBatch) {
+    bool same = n_host[0] >= 128 && n_host[0] <= 1024;
+    for (int64_t i = 1; i < batch && same; ++i) same = n_host[i] == n_host[0];
+    const trinv_opts o = resolve_opts(opts);
+    if (same && (o.leaf == 0 || o.leaf == 16))
+      carve_levels(c, mode, batch, n_host[0], level_leaf(mode, n_host[0], o.leaf));
+  }
   return c.used;
 }
 
@@ -64,7 +94,24 @@ extern "C" int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t
   WsPersistent w = carve_persistent(c, batch);
   if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  {
+  if (level_path(batch, n_host, off_host)) {
+    const int64_t n = n_host[0], leaf = level_leaf(mode, n, o.leaf);
+    WsLevels wl = carve_levels(c, mode, batch, n, leaf);
+    if (!c.ok()) return TRINV_ERR_WORKSPACE;
+    HIP_TRY(launch_fill_u64(wl.first_bad, ~0ull, batch, s));
+    if (mode == TRINV_F64) {
+      HIP_TRY(launch_leaf<double>(n, (const double*)L_packed, n, (double*)X_packed, n, n * n, batch, (int)leaf,
+                                  o.unit_diag, nullptr, nullptr, 0, 0, wl.first_bad, 1, s));
+      HIP_TRY(run_levels<double, double>(n, (const double*)L_packed, n, (double*)X_packed, n, n * n, batch, leaf,
+                                         (double*)wl.T, s));
+    } else {
+      HIP_TRY(launch_leaf<float>(n, (const float*)L_packed, n, (float*)X_packed, n, n * n, batch, (int)leaf,
+                                 o.unit_diag, nullptr, nullptr, 0, 0, wl.first_bad, 1, s));
+      HIP_TRY(run_levels<float, float>(n, (const float*)L_packed, n, (float*)X_packed, n, n * n, batch, leaf,
+                                       (float*)wl.T, s));
+    }
+    HIP_TRY(launch_status_to_i32(wl.first_bad, status_dev, batch, s));
+  } else {
     ProfLaunch pl(mode == TRINV_F32 ? "f32_batched" : "f64_batched", flops, bytes, s);
     if (mode == TRINV_F32)
       HIP_TRY(launch_batched<float>(batch, n_dev, off_dev, (const float*)L_packed, (float*)X_packed, status_dev,

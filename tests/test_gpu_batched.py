@@ -196,3 +196,20 @@ def test_batched_4096_configuration(P):
     assert np.all(st.cpu().numpy() == 0)
     r, f = check(mats, unpack(X.cpu().numpy(), offs, sizes), TOL["f32"], oracle_every=16)
     print(f"4096: worst residual {r:.3e}, worst forward error {f:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("n,batch", [(300, 10), (1024, 3), (64, 40), (130, 300)])
+def test_uniform_batches(P, dt, n, batch):
+    """Equal orders: a few large matrices run the batched level products, many
+    or small ones the persistent kernel; both against the oracle."""
+    import torch
+
+    banner(f"batched uniform {dt} n={n} batch={batch}")
+    sizes = [n] * batch
+    npdt = np.float32 if dt == "f32" else np.float64
+    packed, offs, mats = make_batch(sizes, npdt, seed0=900)
+    X, st = P.tril_inverse_batched(torch.from_numpy(packed).cuda(), sizes, offs, dt)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    check(mats, unpack(X.cpu().numpy(), offs, sizes), TOL[dt], oracle_every=max(1, batch // 8))
