@@ -231,7 +231,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--seed", type=int, default=5)
-    ap.add_argument("--paths", default="bf16_refine,f64")
+    ap.add_argument("--paths", default="bf16_refine,f16_refine,f64")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",

@@ -179,7 +179,7 @@ hipError_t plain_inverse(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, 
   {
     const double nl = (double)((n + leaf - 1) / leaf), b = (double)leaf;
     ProfLaunch pl(sizeof(T) == 8 ? "leaf_f64" : "leaf_f32", nl * b * b * b / 3.0, nl * b * b * sizeof(T), s);
-    e = launch_leaf<T>(n, Lin, ldin, Xout, ldout, 0, 1, (int)leaf, o.unit_diag, nullptr, nullptr, 0, 0, w.status, 0, s);
+    e = launch_leaf<T>(n, Lin, ldin, Xout, ldout, 0, 1, (int)leaf, o.unit_diag, nullptr, nullptr, 0, 0, 1.0, w.status, 0, s);
   }
   if (e != hipSuccess) return e;
   if ((e = run_levels<T, T>(n, Lin, ldin, Xout, ldout, 0, 1, leaf, (T*)w.T, s)) != hipSuccess) return e;

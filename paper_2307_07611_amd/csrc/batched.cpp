@@ -101,12 +101,12 @@ extern "C" int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t
     HIP_TRY(launch_fill_u64(wl.first_bad, ~0ull, batch, s));
     if (mode == TRINV_F64) {
       HIP_TRY(launch_leaf<double>(n, (const double*)L_packed, n, (double*)X_packed, n, n * n, batch, (int)leaf,
-                                  o.unit_diag, nullptr, nullptr, 0, 0, wl.first_bad, 1, s));
+                                  o.unit_diag, nullptr, nullptr, 0, 0, 1.0, wl.first_bad, 1, s));
       HIP_TRY(run_levels<double, double>(n, (const double*)L_packed, n, (double*)X_packed, n, n * n, batch, leaf,
                                          (double*)wl.T, s));
     } else {
       HIP_TRY(launch_leaf<float>(n, (const float*)L_packed, n, (float*)X_packed, n, n * n, batch, (int)leaf,
-                                 o.unit_diag, nullptr, nullptr, 0, 0, wl.first_bad, 1, s));
+                                 o.unit_diag, nullptr, nullptr, 0, 0, 1.0, wl.first_bad, 1, s));
       HIP_TRY(run_levels<float, float>(n, (const float*)L_packed, n, (float*)X_packed, n, n * n, batch, leaf,
                                        (float*)wl.T, s));
     }

@@ -47,6 +47,59 @@ __global__ __launch_bounds__(256) void k_sumsq(const T* A, int64_t n, int64_t ld
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// Block-wide maximum of one double per thread (256 threads).
+__device__ __forceinline__ double block_max_256(double v) {
+  __shared__ double red[4];
+  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_maxabs(const T* A, int64_t n, int64_t lda, int lower, int unit,
+                                                int64_t rows_per_block, double* partial) {
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = imin64(n, r0 + rows_per_block);
+  double m = 0.0;
+  for (int64_t i = r0; i < r1; ++i) {
+    const int64_t jmax = lower ? i + 1 : n;
+    for (int64_t j = threadIdx.x; j < jmax; j += 256) {
+      double v = fabs((double)A[i * lda + j]);
+      if (unit && j == i) v = 1.0;
+      m = fmax(m, v);
+    }
+  }
+  m = block_max_256(m);
+  if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_max(const double* partial, int64_t count, double* out) {
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) m = fmax(m, partial[i]);
+  m = block_max_256(m);
+  if (threadIdx.x == 0) out[0] = m;
+}
+
+template <typename T>
+hipError_t launch_maxabs(const T* A, int64_t n, int64_t lda, int lower, int unit, double* partial, int64_t npartial,
+                         double* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t rpb = (n + npartial - 1) / npartial;
+  const int64_t blocks = (n + rpb - 1) / rpb;
+  hipLaunchKernelGGL((k_maxabs<T>), dim3((unsigned)blocks), dim3(256), 0, s, A, n, lda, lower, unit, rpb, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, s, partial, blocks, out);
+  return hipGetLastError();
+}
+template hipError_t launch_maxabs<double>(const double*, int64_t, int64_t, int, int, double*, int64_t, double*,
+                                          hipStream_t);
+template hipError_t launch_maxabs<float>(const float*, int64_t, int64_t, int, int, double*, int64_t, double*,
+                                         hipStream_t);
+
 __global__ __launch_bounds__(256) void k_reduce_sum(const double* partial, int64_t count, double* out) {
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < count; i += 256) s += partial[i];

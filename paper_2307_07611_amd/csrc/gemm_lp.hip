@@ -379,7 +379,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
           for (int e = 0; e < 4; ++e) {
             const int64_t row = row0 + e;
             const double v = alpha * (double)blk[4 * q + e];
-            o[e] = to_lp<F16>((float)v);
+            o[e] = to_lp<F16>((float)(v * a.lp_scale));
             if (full || (colok && row < M)) {
               a.X[z * a.x_bstride + row * a.ldx + col] = v;
               ((u16*)a.Xlp)[z * a.xlp_bstride + row * a.ldxlp + col] = o[e];
@@ -410,24 +410,26 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
                 rv = fma(-lii, xij, 1.0);
               } else {
                 const double lij = a.L[row * a.ldl + col];
-                rv = -(double)blk[4 * q + e] - lii * xij - lij * xjj;
+                rv = -(alpha * (double)blk[4 * q + e]) - lii * xij - lij * xjj;
               }
               a.R32[row * a.ldr + col] = (float)rv;
               sq += rv * rv;
               sqx += xij * xij;
             }
-            o[e] = to_lp<F16>((float)rv);
+            o[e] = to_lp<F16>((float)(rv * a.lp_scale));
           }
-          u16* dst = (u16*)a.Rt + col * a.ldrt + row0;
-          if (full || (colok && row0 + 3 < M)) {
-            uint2 v;
-            v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
-            v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
-            *(uint2*)dst = v;
-          } else if (colok) {
+          if (a.Rt) {  // uniform: the FP16 path writes R in low precision in a separate pass
+            u16* dst = (u16*)a.Rt + col * a.ldrt + row0;
+            if (full || (colok && row0 + 3 < M)) {
+              uint2 v;
+              v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
+              v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
+              *(uint2*)dst = v;
+            } else if (colok) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (row0 + e < M) dst[e] = o[e];
+              for (int e = 0; e < 4; ++e)
+                if (row0 + e < M) dst[e] = o[e];
+            }
           }
         } else {  // kLpEpCorr
 #pragma unroll
@@ -437,7 +439,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
               const double xii = a.dX[row];
               const double rij = (double)a.R32[row * a.ldr + col];
               double* px = a.X + row * a.ldx + col;
-              *px = *px + xii * rij + (double)blk[4 * q + e];
+              *px = *px + xii * rij + alpha * (double)blk[4 * q + e];
             }
           }
         }

@@ -10,13 +10,14 @@ namespace trinv {
 // Inverts the diagonal leaf blocks of order `leaf` (the last one may be
 // shorter) of a strided batch of lower matrices. If Xlp / Xlpt are non-null,
 // a BF16 (lp_is_f16 = 0) or FP16 (1) copy of each leaf block is stored there
-// too, row-major / transposed (leading dimension ldxl, same batch stride). first_bad: atomic minimum of
+// too, row-major / transposed (leading dimension ldxl, same batch stride),
+// of the values times lp_scale (a power of two). first_bad: atomic minimum of
 // the 1-based indices of exact zero pivots (init to all ones); one word for
 // the whole call, or one per matrix (per_matrix_status = 1).
 template <typename T>
 hipError_t launch_leaf(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int64_t stride, int64_t batch,
-                       int leaf, int unit, void* Xlp, void* Xlpt, int lp_is_f16, int64_t ldxl, uint64_t* first_bad,
-                       int per_matrix_status, hipStream_t s);
+                       int leaf, int unit, void* Xlp, void* Xlpt, int lp_is_f16, int64_t ldxl, double lp_scale,
+                       uint64_t* first_bad, int per_matrix_status, hipStream_t s);
 
 // ---------------------------------------------------------------- tile products
 // A tile product D = alpha * op(A) * op(B) over a set of output tiles
@@ -101,6 +102,11 @@ hipError_t launch_sumsq(const T* A, int64_t n, int64_t lda, int lower, int unit,
 hipError_t launch_reduce_sum(const double* partial, int64_t count, double* out, hipStream_t s);
 // out[0] = sum of v[i]^2 (one block, fixed order).
 hipError_t launch_sumsq_vec(const double* v, int64_t count, double* out, hipStream_t s);
+// out[0] = max |A(i, j)| over the lower triangle (or all of A), diagonal
+// taken as 1 if unit; partial: npartial doubles of scratch.
+template <typename T>
+hipError_t launch_maxabs(const T* A, int64_t n, int64_t lda, int lower, int unit, double* partial, int64_t npartial,
+                         double* out, hipStream_t s);
 // status[i] = first_bad[i] == all ones ? 0 : first_bad[i]  (int32 per matrix).
 hipError_t launch_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count, hipStream_t s);
 // B = A^T for an n x n matrix.

@@ -24,7 +24,7 @@ template <typename T, typename TL, int B>
 __global__ __launch_bounds__(256) void k_leaf_inverse(int64_t n, const T* __restrict__ L, int64_t ldl,
                                                       T* __restrict__ X, int64_t ldx, int64_t stride,
                                                       int unit, TL* __restrict__ Xlp, TL* __restrict__ Xlpt,
-                                                      int64_t ldxl, int64_t* __restrict__ first_bad,
+                                                      int64_t ldxl, double lp_scale, int64_t* __restrict__ first_bad,
                                                       int per_matrix_status) {
   constexpr int P = 256 / B;  // lanes per column
   constexpr int PACK = B * (B + 1) / 2;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_leaf_inverse(int64_t n, const T* __rest
     const int i = idx / bs, jj = idx % bs;
     const T v = (jj <= i) ? Xp[i * (i + 1) / 2 + jj] : (T)0;
     Xb[(int64_t)i * ldx + jj] = v;
-    if (Xlp) Xlp[(int64_t)blockIdx.y * stride + (r0 + i) * ldxl + r0 + jj] = (TL)(float)v;
+    if (Xlp) Xlp[(int64_t)blockIdx.y * stride + (r0 + i) * ldxl + r0 + jj] = (TL)(float)((double)v * lp_scale);
   }
   // Transposed low-precision copy: element (i, jj) of the leaf at [jj][i],
   // written with consecutive threads along i (coalesced).
@@ -83,24 +83,24 @@ __global__ __launch_bounds__(256) void k_leaf_inverse(int64_t n, const T* __rest
     for (int idx = tid; idx < bs * bs; idx += 256) {
       const int jj = idx / bs, i = idx % bs;
       const T v = (jj <= i) ? Xp[i * (i + 1) / 2 + jj] : (T)0;
-      Xlpt[(int64_t)blockIdx.y * stride + (r0 + jj) * ldxl + r0 + i] = (TL)(float)v;
+      Xlpt[(int64_t)blockIdx.y * stride + (r0 + jj) * ldxl + r0 + i] = (TL)(float)((double)v * lp_scale);
     }
   }
 }
 
 template <typename T, typename TL>
 static hipError_t launch_leaf_t(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int64_t stride,
-                                int64_t batch, int leaf, int unit, TL* Xlp, TL* Xlpt, int64_t ldxl,
+                                int64_t batch, int leaf, int unit, TL* Xlp, TL* Xlpt, int64_t ldxl, double lp_scale,
                                 uint64_t* first_bad, int per_matrix_status, hipStream_t s) {
   const int64_t nleaves = (n + leaf - 1) / leaf;
   if (nleaves <= 0 || batch <= 0) return hipSuccess;
   dim3 grid((unsigned)nleaves, (unsigned)batch), block(256);
   int64_t* fb = (int64_t*)first_bad;
   switch (leaf) {
-    case 16: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 16>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, fb, per_matrix_status); break;
-    case 32: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 32>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, fb, per_matrix_status); break;
-    case 64: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 64>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, fb, per_matrix_status); break;
-    case 128: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 128>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, fb, per_matrix_status); break;
+    case 16: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 16>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status); break;
+    case 32: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 32>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status); break;
+    case 64: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 64>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status); break;
+    case 128: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 128>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -108,18 +108,18 @@ static hipError_t launch_leaf_t(int64_t n, const T* L, int64_t ldl, T* X, int64_
 
 template <typename T>
 hipError_t launch_leaf(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int64_t stride, int64_t batch,
-                       int leaf, int unit, void* Xlp, void* Xlpt, int lp_is_f16, int64_t ldxl, uint64_t* first_bad,
-                       int per_matrix_status, hipStream_t s) {
+                       int leaf, int unit, void* Xlp, void* Xlpt, int lp_is_f16, int64_t ldxl, double lp_scale,
+                       uint64_t* first_bad, int per_matrix_status, hipStream_t s) {
   if (Xlp && lp_is_f16)
     return launch_leaf_t<T, _Float16>(n, L, ldl, X, ldx, stride, batch, leaf, unit, (_Float16*)Xlp, (_Float16*)Xlpt,
-                                      ldxl, first_bad, per_matrix_status, s);
+                                      ldxl, lp_scale, first_bad, per_matrix_status, s);
   return launch_leaf_t<T, __bf16>(n, L, ldl, X, ldx, stride, batch, leaf, unit, (__bf16*)Xlp, (__bf16*)Xlpt, ldxl,
-                                  first_bad, per_matrix_status, s);
+                                  lp_scale, first_bad, per_matrix_status, s);
 }
 
 template hipError_t launch_leaf<double>(int64_t, const double*, int64_t, double*, int64_t, int64_t, int64_t, int,
-                                        int, void*, void*, int, int64_t, uint64_t*, int, hipStream_t);
+                                        int, void*, void*, int, int64_t, double, uint64_t*, int, hipStream_t);
 template hipError_t launch_leaf<float>(int64_t, const float*, int64_t, float*, int64_t, int64_t, int64_t, int, int,
-                                       void*, void*, int, int64_t, uint64_t*, int, hipStream_t);
+                                       void*, void*, int, int64_t, double, uint64_t*, int, hipStream_t);
 
 }  // namespace trinv

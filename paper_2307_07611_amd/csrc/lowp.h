@@ -13,9 +13,10 @@ enum LpEpilogue {
   kLpEpT = 0,      // store alpha*acc transposed (low precision): T for the next product
   kLpEpX21 = 1,    // X21 = alpha*acc: FP64 X, low-precision row-major and transposed copies,
                    // zero the FP64 X12 block
-  kLpEpResid = 2,  // R = I - L X assembled in FP64 from acc = N_L N_X (lower tiles):
-                   // FP32 R, low-precision transposed R, per-tile ||R||^2 and ||X||^2
-  kLpEpCorr = 3    // X <- X + D_X R + acc (acc = N_X R), lower tiles, in place
+  kLpEpResid = 2,  // R = I - L X assembled in FP64 from alpha*acc = N_L N_X (lower tiles):
+                   // FP32 R, low-precision transposed R (if Rt is set), per-tile
+                   // ||R||^2 and ||X||^2
+  kLpEpCorr = 3    // X <- X + D_X R + alpha*acc (alpha*acc = N_X R), lower tiles, in place
 };
 
 // All operands in element units of their own type. Low-precision operands:
@@ -51,6 +52,10 @@ struct LpGemmArgs {
   int64_t ldrt;
   double* tile_sq;   // kLpEpResid: per-tile sum of R^2
   double* tile_sqx;  // kLpEpResid: per-tile sum of X^2 (lower triangle)
+  // Power-of-two factor applied to the values before they are stored in low
+  // precision (kLpEpX21 copies, kLpEpResid's Rt); the accumulator itself is
+  // scaled by alpha in every epilogue.
+  double lp_scale;
 };
 
 struct LpConfig {
@@ -64,13 +69,16 @@ struct LpConfig {
 hipError_t launch_gemm_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_t s);
 int64_t gemm_lp_tiles(const GemmBatch& bt, int tiles);
 
-// Low-precision slices of a lower-triangular FP64 matrix (64 x 64 tiles of the
-// lower triangle; elements above the diagonal are written as 0 inside
-// diagonal tiles and not at all elsewhere):
-//   hi = round(v), lo = round(v - hi) (round-to-nearest-even in the target type);
-// each output is optional; "t" outputs are transposed (element (i,j) at [j][i]).
-// diag (optional) receives the FP64 diagonal.
+// Low-precision slices of a lower-triangular FP64 matrix times a power-of-two
+// scale (64 x 64 tiles of the lower triangle; elements above the diagonal are
+// written as 0 inside diagonal tiles and not at all elsewhere):
+//   hi = round(scale v), lo = round(scale v - hi) (round-to-nearest-even in
+// the target type); each output is optional; "t" outputs are transposed
+// (element (i,j) at [j][i]). diag (optional) receives the unscaled diagonal.
 hipError_t launch_split(const double* S, int64_t lds, int64_t n, int f16, void* hi, void* lo, void* hi_t, void* lo_t,
-                        int64_t ldo, double* diag, int unit, hipStream_t s);
+                        int64_t ldo, double* diag, int unit, double scale, hipStream_t s);
+// The transposed hi slice only, from an FP32 lower-triangular matrix.
+hipError_t launch_split_f32(const float* S, int64_t lds, int64_t n, int f16, void* hi_t, int64_t ldo, double scale,
+                            hipStream_t s);
 
 }  // namespace trinv

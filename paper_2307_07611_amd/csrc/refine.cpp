@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "api_internal.h"
 #include "lowp.h"
@@ -70,7 +71,10 @@ WsRefine carve_refine(Carve& c, int64_t n, int64_t leaf) {
 }
 
 // Level products of the forward recursion on low-precision MFMA.
-hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, const WsRefine& w, hipStream_t s) {
+// sL, sX: power-of-two scales of the L and X planes (1 for BF16); T is stored
+// with the scale of X.
+hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, const WsRefine& w, double sL,
+                     double sX, hipStream_t s) {
   const int64_t ldp = w.ldp;
   for (const Level& lv : levels_of(n, leaf)) {
     const int64_t hA = lv.hA, span = lv.span, ldt = t_ld(hA);
@@ -85,7 +89,8 @@ hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, c
     g1.ldb = ldp;
     g1.b_bstride = stp;
     g1.bt = {lv.nmerge, 1, hA, hA, hA, lv.hB_last, hA, hA};
-    g1.alpha = 1.0;
+    g1.alpha = 1.0 / sL;  // acc = (sL C)(sX A^-1); T is kept scaled by sX
+    g1.lp_scale = 1.0;
     g1.Ot = w.Tt;
     g1.ldot = ldt;
     g1.ot_bstride = hA * ldt;
@@ -106,7 +111,8 @@ hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, c
     g2.ldb = ldt;
     g2.b_bstride = hA * ldt;
     g2.bt = {lv.nmerge, 1, hA, hA, hA, lv.hB_last, hA, lv.hB_last};
-    g2.alpha = -1.0;
+    g2.alpha = -1.0 / (sX * sX);  // acc = (sX B^-1)(sX T)
+    g2.lp_scale = sX;
     g2.X = X + hA * ldx;
     g2.ldx = ldx;
     g2.x_bstride = stx;
@@ -131,6 +137,21 @@ hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, c
 
 double tri_flops(double n) { return n * (n - 1) * (n - 2) / 3.0; }  // strictly-lower x strictly-lower
 
+// Power of two s with m * s < 2^e (1 for m = 0 or non-finite m).
+double pow2_scale(double m, int e) {
+  if (!(m > 0.0) || !std::isfinite(m)) return 1.0;
+  int x = 0;
+  std::frexp(m, &x);  // m < 2^x
+  return std::ldexp(1.0, e - x);
+}
+
+// Host copy of one reduction result.
+hipError_t read_scalar(const double* d, double* h, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
 }  // namespace
 
 size_t refine_workspace_bytes(int mode, int64_t n, const trinv_opts& o, int64_t leaf) {
@@ -147,7 +168,6 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   if (o.upper) return TRINV_ERR_UNSUPPORTED;
   if (leaf < 32) return TRINV_ERR_ARG;
   const int f16 = mode == TRINV_F16_REFINE;
-  if (f16) return TRINV_ERR_UNSUPPORTED;  // FP16 slices need row/column scaling (not built yet)
   Carve c(ws, ws_bytes);
   WsRefine w = carve_refine(c, n, leaf);
   if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
@@ -155,17 +175,37 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   const double dn = (double)n;
 
   HIP_TRY(launch_fill_u64(w.status, ~0ull, 1, s));
+  // FP16 planes carry one power-of-two scale each (exact, undone through the
+  // epilogues' alpha) so that the values sit in FP16's normal range; BF16 has
+  // the exponent range of FP32 and uses 1. L: from max |L|; X during the
+  // forward: from 1 / min |L_ii| (the diagonal of X) with 2^5 of headroom;
+  // X during refinement: from max |X|; R: from ||R||_F (>= max |R_ij|).
+  double sL = 1.0, sXf = 1.0;
+  if (f16) {
+    double mx = 0.0;
+    HIP_TRY(launch_maxabs<double>(L, n, ldl, 1, o.unit_diag, w.partial, kPart, w.scal + 6, s));
+    HIP_TRY(read_scalar(w.scal + 6, &mx, s));
+    sL = pow2_scale(mx, 14);
+  }
   {  // staging: L -> hi / lo slices (row-major) and diag(L)
     ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + 4), s);
-    HIP_TRY(launch_split(L, ldl, n, f16, w.Lhi, w.Llo, nullptr, nullptr, ldp, w.dL, o.unit_diag, s));
+    HIP_TRY(launch_split(L, ldl, n, f16, w.Lhi, w.Llo, nullptr, nullptr, ldp, w.dL, o.unit_diag, sL, s));
+  }
+  if (f16) {
+    std::vector<double> d((size_t)n);
+    HIP_TRY(hipMemcpyAsync(d.data(), w.dL, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double mn = INFINITY;
+    for (double v : d) mn = std::min(mn, std::fabs(v));
+    if (mn > 0.0) sXf = pow2_scale(1.0 / mn, 11);
   }
   {  // leaves in FP64, with row-major and transposed low-precision copies
     const double nl = (double)((n + leaf - 1) / leaf), b = (double)leaf;
     ProfLaunch pl("leaf_f64", nl * b * b * b / 3.0, nl * b * b * (8 + 8 + 4), s);
-    HIP_TRY(launch_leaf<double>(n, L, ldl, X, ldx, 0, 1, (int)leaf, o.unit_diag, w.Xb, w.Xbt, f16, ldp, w.status, 0,
-                                s));
+    HIP_TRY(launch_leaf<double>(n, L, ldl, X, ldx, 0, 1, (int)leaf, o.unit_diag, w.Xb, w.Xbt, f16, ldp, sXf,
+                                w.status, 0, s));
   }
-  HIP_TRY(lp_levels(n, X, ldx, leaf, f16, w, s));
+  HIP_TRY(lp_levels(n, X, ldx, leaf, f16, w, sL, sXf, s));
   // ||tril(L)||^2 and sum of diag(L)^2 once
   HIP_TRY(launch_sumsq<double>(L, n, ldl, 1, o.unit_diag, w.partial, kPart, w.scal + 2, s));
   HIP_TRY(launch_sumsq_vec(w.dL, n, w.scal + 3, s));
@@ -185,9 +225,16 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   const double eps_split = f16 ? std::ldexp(1.0, -22) : std::ldexp(1.0, -16);
   for (;;) {
     // residual of the current X
+    double sX = 1.0;
+    if (f16) {
+      double mx = 0.0;
+      HIP_TRY(launch_maxabs<double>(X, n, ldx, 1, 0, w.partial, kPart, w.scal + 6, s));
+      HIP_TRY(read_scalar(w.scal + 6, &mx, s));
+      sX = pow2_scale(mx, 14);
+    }
     {
       ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + 6), s);
-      HIP_TRY(launch_split(X, ldx, n, f16, w.Xb, nullptr, w.Xbt, w.Xtlo, ldp, w.dX, 0, s));
+      HIP_TRY(launch_split(X, ldx, n, f16, w.Xb, nullptr, w.Xbt, w.Xtlo, ldp, w.dX, 0, sX, s));
     }
     if (resid_fp64 < 0) {
       HIP_TRY(launch_sumsq<double>(X, n, ldx, 1, 0, w.partial, kPart, w.scal + 4, s));
@@ -241,7 +288,8 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gr.Bt_lo = w.Xtlo;
     gr.ldb = ldp;
     gr.bt = bt;
-    gr.alpha = 1.0;
+    gr.alpha = 1.0 / (sL * sX);  // acc = (sL N_L)(sX N_X)
+    gr.lp_scale = 1.0;
     gr.X = X;
     gr.ldx = ldx;
     gr.L = L;
@@ -250,7 +298,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gr.dX = w.dX;
     gr.R32 = w.R32;
     gr.ldr = n;
-    gr.Rt = w.Rt;
+    gr.Rt = f16 ? nullptr : w.Rt;  // FP16: written below, once ||R|| is known
     gr.ldrt = ldp;
     gr.tile_sq = w.tile_sq;
     gr.tile_sqx = w.tile_sqx;
@@ -285,6 +333,12 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     if (!std::isfinite(rho)) return TRINV_ERR_NONFINITE;
     if (rho <= o.tol) return TRINV_OK;
     if (iter >= o.max_iter) return TRINV_ERR_NOT_CONVERGED;
+    double sR = 1.0;
+    if (f16) {  // FP16 R for the correction's B operand, scaled by ||R||_F
+      sR = pow2_scale(std::sqrt(h[0]), 14);
+      ProfLaunch pl("split", 0.0, dn * dn / 2 * (4 + 2), s);
+      HIP_TRY(launch_split_f32(w.R32, n, n, 1, w.Rt, ldp, sR, s));
+    }
     // correction: X <- X + D_X R + N_X R
     LpGemmArgs gc{};
     gc.A_hi = w.Xb;
@@ -292,7 +346,8 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gc.Bt_hi = w.Rt;
     gc.ldb = ldp;
     gc.bt = bt;
-    gc.alpha = 1.0;
+    gc.alpha = 1.0 / (sX * sR);  // acc = (sX N_X)(sR R)
+    gc.lp_scale = 1.0;
     gc.X = X;
     gc.ldx = ldx;
     gc.dX = w.dX;

@@ -1,9 +1,10 @@
-// Staging casts of the mixed-precision path: an FP64 lower-triangular matrix
-// is cut into low-precision slices hi = round(v) and lo = round(v - hi)
-// (round-to-nearest-even in BF16 or FP16; v - hi is exact in FP64), written
-// row-major and/or transposed (through a 64 x 64 LDS tile so both stores are
-// coalesced), plus the FP64 diagonal. HBM-bound: one read of the lower
-// triangle, 2 bytes written per requested slice and element.
+// Staging casts of the mixed-precision path: a lower-triangular FP64 (or FP32)
+// matrix, times a power-of-two scale s, is cut into low-precision slices
+// hi = round(s v) and lo = round(s v - hi) (round-to-nearest-even in BF16 or
+// FP16; s v and s v - hi are exact in FP64), written row-major and/or
+// transposed (through a 64 x 64 LDS tile so both stores are coalesced), plus
+// the unscaled FP64 diagonal. HBM-bound: one read of the lower triangle,
+// 2 bytes written per requested slice and element.
 #include "common.h"
 #include "lowp.h"
 
@@ -26,11 +27,11 @@ __device__ __forceinline__ u16 lp_bits(double v, double* back) {
 }  // namespace
 
 // Grid: one block per 64 x 64 tile of the lower triangle (tile row it >= tile col jt).
-template <int F16>
-__global__ __launch_bounds__(256) void k_split(const double* __restrict__ S, int64_t lds, int64_t n,
+template <int F16, typename TS>
+__global__ __launch_bounds__(256) void k_split(const TS* __restrict__ S, int64_t lds, int64_t n,
                                                u16* __restrict__ hi, u16* __restrict__ lo, u16* __restrict__ hi_t,
                                                u16* __restrict__ lo_t, int64_t ldo, double* __restrict__ diag,
-                                               int unit) {
+                                               int unit, double scale) {
   __shared__ u16 th[64][66];
   __shared__ u16 tl[64][66];
   const int64_t q = blockIdx.x;
@@ -44,9 +45,10 @@ __global__ __launch_bounds__(256) void k_split(const double* __restrict__ S, int
     const int64_t i = i0 + r, j = j0 + tx;
     u16 h = 0, l = 0;
     if (i < n && j < n) {
-      double v = (j <= i) ? S[i * lds + j] : 0.0;
+      double v = (j <= i) ? (double)S[i * lds + j] : 0.0;
       if (unit && i == j) v = 1.0;
       if (i == j && diag) diag[i] = v;
+      v *= scale;
       double hb;
       h = lp_bits<F16>(v, &hb);
       double lb;
@@ -68,17 +70,28 @@ __global__ __launch_bounds__(256) void k_split(const double* __restrict__ S, int
   }
 }
 
-hipError_t launch_split(const double* S, int64_t lds, int64_t n, int f16, void* hi, void* lo, void* hi_t, void* lo_t,
-                        int64_t ldo, double* diag, int unit, hipStream_t s) {
+template <typename TS>
+static hipError_t split_t(const TS* S, int64_t lds, int64_t n, int f16, void* hi, void* lo, void* hi_t, void* lo_t,
+                          int64_t ldo, double* diag, int unit, double scale, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t T = (n + 63) / 64, blocks = T * (T + 1) / 2;
   if (f16)
-    hipLaunchKernelGGL(k_split<1>, dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, (u16*)hi, (u16*)lo, (u16*)hi_t,
-                       (u16*)lo_t, ldo, diag, unit);
+    hipLaunchKernelGGL((k_split<1, TS>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, (u16*)hi, (u16*)lo,
+                       (u16*)hi_t, (u16*)lo_t, ldo, diag, unit, scale);
   else
-    hipLaunchKernelGGL(k_split<0>, dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, (u16*)hi, (u16*)lo, (u16*)hi_t,
-                       (u16*)lo_t, ldo, diag, unit);
+    hipLaunchKernelGGL((k_split<0, TS>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, (u16*)hi, (u16*)lo,
+                       (u16*)hi_t, (u16*)lo_t, ldo, diag, unit, scale);
   return hipGetLastError();
+}
+
+hipError_t launch_split(const double* S, int64_t lds, int64_t n, int f16, void* hi, void* lo, void* hi_t, void* lo_t,
+                        int64_t ldo, double* diag, int unit, double scale, hipStream_t s) {
+  return split_t<double>(S, lds, n, f16, hi, lo, hi_t, lo_t, ldo, diag, unit, scale, s);
+}
+
+hipError_t launch_split_f32(const float* S, int64_t lds, int64_t n, int f16, void* hi_t, int64_t ldo, double scale,
+                            hipStream_t s) {
+  return split_t<float>(S, lds, n, f16, nullptr, nullptr, hi_t, nullptr, ldo, nullptr, 0, scale, s);
 }
 
 }  // namespace trinv

@@ -31,19 +31,20 @@ def trinv():
     return P
 
 
-def run(trinv, L, **kw):
+def run(trinv, L, mode="bf16_refine", **kw):
     import torch
 
-    X, info = trinv.tril_inverse(L, "bf16_refine", return_info=True, **kw)
+    X, info = trinv.tril_inverse(L, mode, return_info=True, **kw)
     torch.cuda.synchronize()
     return X, info
 
 
+@pytest.mark.parametrize("mode", ["bf16_refine", "f16_refine"])
 @pytest.mark.parametrize("n,leaf", [(256, 64), (300, 64), (1024, 64), (1500, 128), (2048, 128)])
-def test_bf16_refine_vs_oracle(trinv, n, leaf):
-    banner(f"bf16_refine n={n} leaf={leaf}")
+def test_refine_vs_oracle(trinv, mode, n, leaf):
+    banner(f"{mode} n={n} leaf={leaf}")
     L = synth.lower_triangular(n, 60 + n)
-    X, info = run(trinv, dev(L), leaf=leaf)
+    X, info = run(trinv, dev(L), mode, leaf=leaf)
     Xg = host(X)
     r = oracle.residuals(L, Xg)
     print(f"n={n}: iterations={info['iterations']} rho_gpu={info['rel_residual']:.3e} "
@@ -56,14 +57,16 @@ def test_bf16_refine_vs_oracle(trinv, n, leaf):
     assert abs(info["rel_residual"] - r["rel_lx"]) < 1e-12
 
 
-def test_bf16_exact_bidiagonal(trinv):
+@pytest.mark.parametrize("mode", ["bf16_refine", "f16_refine"])
+def test_exact_bidiagonal(trinv, mode):
     """All values +-1: every product and every partial sum is exact in BF16 /
-    FP32, so X is the exact all-ones lower triangle and no correction runs."""
+    FP16 (with power-of-two scales) and FP32, so X is the exact all-ones lower
+    triangle and no correction runs."""
     n = 1000
-    banner(f"bf16_refine bidiagonal -1 n={n}")
+    banner(f"{mode} bidiagonal -1 n={n}")
     L = np.eye(n)
     L[np.arange(1, n), np.arange(n - 1)] = -1.0
-    X, info = run(trinv, dev(L), leaf=64)
+    X, info = run(trinv, dev(L), mode, leaf=64)
     np.testing.assert_array_equal(host(X), np.tril(np.ones((n, n))))
     assert info["iterations"] == 0 and info["rel_residual"] == 0.0
 
@@ -81,14 +84,15 @@ def test_bf16_not_converged_reports_forward_residual(trinv):
     assert e.value.info["iterations"] == 0
 
 
-def test_bf16_singular(trinv):
+@pytest.mark.parametrize("mode", ["bf16_refine", "f16_refine"])
+def test_singular(trinv, mode):
     from paper_2307_07611_amd import _lib
 
-    banner("bf16_refine singular n=512")
+    banner(f"{mode} singular n=512")
     L = synth.lower_triangular(512, 3)
     L[300, 300] = 0.0
     with pytest.raises(_lib.TrinvError) as e:
-        trinv.tril_inverse(dev(L), "bf16_refine", leaf=64)
+        trinv.tril_inverse(dev(L), mode, leaf=64)
     assert e.value.code == _lib.ERR_SINGULAR and e.value.info["first_bad_index"] == 301
 
 
@@ -109,16 +113,17 @@ def test_bf16_ill_conditioned_is_honest(trinv):
         assert e.code in (_lib.ERR_NOT_CONVERGED, _lib.ERR_NONFINITE)
 
 
-def test_bf16_n16384_configuration(trinv):
+@pytest.mark.parametrize("mode", ["bf16_refine", "f16_refine"])
+def test_refine_n16384_configuration(trinv, mode):
     """Configuration size: residual by the FP64-MFMA helper, sampled columns
     against the oracle."""
     import torch
 
     n = 16384
-    banner(f"bf16_refine n={n} leaf=128 seed=5")
+    banner(f"{mode} n={n} leaf=128 seed=5")
     L = synth.lower_triangular(n, 5)
     Ld = dev(L)
-    X, info = run(trinv, Ld, leaf=128)
+    X, info = run(trinv, Ld, mode, leaf=128)
     r = trinv.residual(Ld, X)
     print(f"n={n}: iterations={info['iterations']} rho_gpu={info['rel_residual']:.3e} rho_fp64={r['rel']:.3e}",
           flush=True)
