@@ -7,10 +7,11 @@
 // v_mfma_f32_32x32x16_{bf16,f16}; each wave owns a 128 x 128 sub-tile
 // (4 x 4 blocks of 32 x 32, 256 FP32 accumulators per lane). Both operands
 // are k-contiguous in memory (B is stored transposed), so a K step is staged
-// with 16-byte loads into two LDS buffers and every MFMA operand is one
-// 16-byte LDS read. Lane layouts (measured on gfx950): lane l supplies
-// A(l%32, 8(l/32)+e) and B(8(l/32)+e, l%32), e = 0..7, and receives
-// D(8(r/4) + 4(l/32) + r%4, l%32) in register r.
+// by direct global -> LDS 16-byte loads into one of four LDS buffers, issued
+// three stages ahead, and every MFMA operand is one 16-byte LDS read. Lane
+// layouts (measured on gfx950): lane l supplies A(l%32, 8(l/32)+e) and
+// B(8(l/32)+e, l%32), e = 0..7, and receives D(8(r/4) + 4(l/32) + r%4, l%32)
+// in register r.
 //
 // The optional 3-product split forms A_hi B_hi + A_hi B_lo + A_lo B_hi in the
 // same accumulator (an operand v is carried as hi = round(v) plus
@@ -42,8 +43,9 @@ constexpr int LT = 256;  // workgroup tile (rows and columns)
 
 template <int NSPLIT>
 struct LpShape {
-  static constexpr int KT = NSPLIT == 1 ? 64 : 32;  // K per LDS stage
+  static constexpr int KT = NSPLIT == 1 ? 32 : 16;  // K per LDS stage
   static constexpr int NT = NSPLIT == 1 ? 2 : 4;    // staged tiles per stage
+  static constexpr int NBUF = 4;                    // LDS stages: loads run NBUF - 1 stages ahead
   static constexpr int CPR = KT / 8;                // 16-byte chunks per tile row
   static constexpr int TILE = LT * KT;              // elements of one staged tile (no padding)
   static constexpr int RPI = 512 / KT;              // tile rows per 1 KB direct-load instruction
@@ -62,6 +64,21 @@ template <int F16>
 __device__ __forceinline__ f32x16 mma(u32x4 a, u32x4 b, f32x16 c) {
   if (F16) return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// Waits (gfx9 s_waitcnt encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8) followed by a workgroup barrier, with no memory fence: the
+// direct global -> LDS loads of newer stages stay in flight across it. VM is
+// the number of this wave's direct loads allowed to remain outstanding; all
+// its LDS reads are complete, so buffers read before the barrier may be
+// refilled after it.
+template <int VM>
+__device__ __forceinline__ void wait_barrier() {
+  static_assert(VM >= 0 && VM < 64, "vmcnt range");
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4));  // lgkmcnt(0), vmcnt(VM)
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
 }
 
 template <int F16>
@@ -121,7 +138,7 @@ template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, in
 __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   typedef LpShape<NSPLIT> S;
   constexpr int KT = S::KT;
-  extern __shared__ __attribute__((aligned(16))) u16 lds[];  // 2 stages x NT tiles x TILE elements
+  extern __shared__ __attribute__((aligned(16))) u16 lds[];  // NBUF stages x NT tiles x TILE elements
   __shared__ double red[2][4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -160,7 +177,9 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   }
   int64_t klo = 0, khi = K;
   if (KLO == kLoN0) klo = n0;
+  if (KLO == kLoBlock) klo = bj * GB * LT;
   if (KHI == kHiM1) khi = imin64(K, m0 + LT);
+  if (KHI == kHiBlock) khi = imin64(K, (bi * GB + GB) * LT);
   klo = (klo / KT) * KT;
 
   // Staging by direct global -> LDS loads: instruction i of wave w fills
@@ -323,32 +342,49 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
     }
   };
 
+  // NBUF-stage pipeline: stage st lives in buffer st % NBUF; its loads were
+  // issued NBUF - 1 stages earlier. Before computing it, each wave waits until
+  // only its loads of the newer stages are outstanding, then the barrier makes
+  // every wave's part visible and frees the buffer of stage st - 1 for stage
+  // st + NBUF - 1.
+  constexpr int NBUF = S::NBUF;
+  constexpr int LPS = S::NT * S::IPW;  // direct loads per thread and stage
   if (klo < khi) {
-    issue(0, 0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    int buf = 0;
-    for (int64_t k0 = klo; k0 < khi; k0 += S::KT) {
-      const u16* base = lds + buf * (S::NT * S::TILE);
-      if (k0 + S::KT < khi) issue(buf ^ 1, k0 + S::KT - klo);
+    const int nst = (int)((khi - klo + S::KT - 1) / S::KT);
+#pragma unroll
+    for (int p = 0; p < NBUF - 1; ++p)
+      if (p < nst) issue(p, (int64_t)p * S::KT);
+    for (int st = 0; st < nst; ++st) {
+      const int buf = st % NBUF;
+      if (st + NBUF - 2 < nst)
+        wait_barrier<(NBUF - 2) * LPS>();
+      else
+        wait_barrier<0>();
+      if (st + NBUF - 1 < nst) issue((st + NBUF - 1) % NBUF, (int64_t)(st + NBUF - 1) * S::KT);
+      const int64_t k0 = klo + (int64_t)st * S::KT;
       bool guard = (k0 + S::KT > K);
       if (AM != 0 && k0 + S::KT > m0 && k0 < m0 + LT) guard = true;
       if (BM != 0 && k0 + S::KT > n0 && k0 < n0 + LT) guard = true;
       if (guard) {
         mask_lds(buf, k0);
-        __syncthreads();
+        wait_barrier<LPS * (NBUF - 1)>();  // LDS writes of the mask visible (loads stay in flight)
       }
-      stage_compute(base);
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      buf ^= 1;
+      stage_compute(lds + buf * (S::NT * S::TILE));
     }
+    wait_barrier<0>();
   }
 
   // ---------------------------------------------------------------- epilogues
   const bool full = (m0 + LT <= M) && (n0 + LT <= N);
   const double alpha = a.alpha;
   double sq = 0.0, sqx = 0.0;
+  // arrays only read by the residual (X, L, diagonals) or by the correction
+  // (R32, diagonal of X): no store of the kernel aliases them
+  const double* __restrict__ Xr = a.X;
+  const double* __restrict__ Lr = a.L;
+  const double* __restrict__ dLr = a.dL;
+  const double* __restrict__ dXr = a.dX;
+  const float* __restrict__ R32r = a.R32;
   static_for<0, 16>([&](auto IJ) {
       constexpr int i = decltype(IJ)::value / 4, j = decltype(IJ)::value % 4;
       const f32x16 blk = acc[i][j];
@@ -396,52 +432,79 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
             for (int e = 0; e < 4; ++e)
               if (row0 + e < M) dst[e] = o[e];
           }
-        } else if (EPI == kLpEpResid) {
-          u16 o[4];
-          const double xjj = colok ? a.dX[col] : 0.0;
+        }
+      }
+      if constexpr (EPI == kLpEpResid || EPI == kLpEpCorr) {
+        // Gather the block's FP64 / FP32 operands first, all loads
+        // unconditional (out-of-triangle lanes read element 0 and discard
+        // it), so that they are in flight together; then compute and store.
+        const bool colok = full || col < N;
+        const int64_t rbase = m0 + wm * 128 + i * 32 + 4 * (lane >> 5);
+        double xv[16], dv[16], ov[16];
+        bool okv[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const int64_t row = row0 + e;
-            double rv = 0.0;
-            if ((full || (colok && row < M)) && col <= row) {
-              const double lii = a.dL[row];
-              const double xij = a.X[row * a.ldx + col];
-              if (row == col) {
-                rv = fma(-lii, xij, 1.0);
-              } else {
-                const double lij = a.L[row * a.ldl + col];
-                rv = -(alpha * (double)blk[4 * q + e]) - lii * xij - lij * xjj;
+            const int k = 4 * q + e;
+            const int64_t row = rbase + 8 * q + e;
+            okv[k] = (full || (colok && row < M)) && col <= row;
+            const int64_t rr = okv[k] ? row : 0, cc = okv[k] ? col : 0;
+            if constexpr (EPI == kLpEpResid) {
+              xv[k] = Xr[rr * a.ldx + cc];
+              ov[k] = Lr[rr * a.ldl + cc];
+              dv[k] = dLr[rr];
+            } else {
+              xv[k] = a.X[rr * a.ldx + cc];
+              ov[k] = (double)R32r[rr * a.ldr + cc];
+              dv[k] = dXr[rr];
+            }
+          }
+        if constexpr (EPI == kLpEpResid) {
+          const double xjj = colok ? dXr[col] : 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t row0 = rbase + 8 * q;
+            u16 o[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int k = 4 * q + e;
+              const int64_t row = row0 + e;
+              double rv = 0.0;
+              if (okv[k]) {
+                if (row == col)
+                  rv = fma(-dv[k], xv[k], 1.0);
+                else
+                  rv = -(alpha * (double)blk[k]) - dv[k] * xv[k] - ov[k] * xjj;
+                a.R32[row * a.ldr + col] = (float)rv;
+                sq += rv * rv;
+                sqx += xv[k] * xv[k];
               }
-              a.R32[row * a.ldr + col] = (float)rv;
-              sq += rv * rv;
-              sqx += xij * xij;
+              o[e] = to_lp<F16>((float)(rv * a.lp_scale));
             }
-            o[e] = to_lp<F16>((float)(rv * a.lp_scale));
-          }
-          if (a.Rt) {  // uniform: the FP16 path writes R in low precision in a separate pass
-            u16* dst = (u16*)a.Rt + col * a.ldrt + row0;
-            if (full || (colok && row0 + 3 < M)) {
-              uint2 v;
-              v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
-              v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
-              *(uint2*)dst = v;
-            } else if (colok) {
+            if (a.Rt) {  // uniform: the FP16 path writes R in low precision in a separate pass
+              u16* dst = (u16*)a.Rt + col * a.ldrt + row0;
+              if (full || (colok && row0 + 3 < M)) {
+                uint2 v;
+                v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
+                v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
+                *(uint2*)dst = v;
+              } else if (colok) {
 #pragma unroll
-              for (int e = 0; e < 4; ++e)
-                if (row0 + e < M) dst[e] = o[e];
+                for (int e = 0; e < 4; ++e)
+                  if (row0 + e < M) dst[e] = o[e];
+              }
             }
           }
-        } else {  // kLpEpCorr
+        } else {  // kLpEpCorr: X <- X + D_X R + alpha acc
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int64_t row = row0 + e;
-            if ((full || (colok && row < M)) && col <= row) {
-              const double xii = a.dX[row];
-              const double rij = (double)a.R32[row * a.ldr + col];
-              double* px = a.X + row * a.ldx + col;
-              *px = *px + xii * rij + alpha * (double)blk[4 * q + e];
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int k = 4 * q + e;
+              const int64_t row = rbase + 8 * q + e;
+              if (okv[k]) a.X[row * a.ldx + col] = xv[k] + dv[k] * ov[k] + alpha * (double)blk[k];
             }
-          }
         }
       }
     });
@@ -482,7 +545,7 @@ static int64_t lp_grid(const GemmBatch& bt, int tiles) {
 template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
 static hipError_t go_lp(const LpGemmArgs& a, hipStream_t s, int64_t total) {
   typedef LpShape<NSPLIT> S;
-  const size_t lds = 2u * S::NT * S::TILE * sizeof(unsigned short);  // two stages
+  const size_t lds = (size_t)S::NBUF * S::NT * S::TILE * sizeof(unsigned short);
   auto k = k_gemm_lp<F16, NSPLIT, AM, BM, TILES, ORDER, KLO, KHI, EPI>;
   static bool attr_set = false;  // per instantiation
   if (!attr_set) {
@@ -504,6 +567,17 @@ static hipError_t dispatch_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_
   if (c.nsplit == 1 && c.amask == 1 && c.bmask == 0 && c.tiles == kAllTiles && c.order == kRowDesc &&
       c.klo == kLoZero && c.khi == kHiM1 && c.epi == kLpEpX21)
     return go_lp<F16, 1, 1, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kLpEpX21>(a, s, total);
+  // residual and correction over block-union K ranges (operands zero outside
+  // their triangles, no masks)
+  if (c.amask == 0 && c.bmask == 0 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoBlock &&
+      c.khi == kHiBlock) {
+    if (c.epi == kLpEpResid && c.nsplit == 3)
+      return go_lp<F16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpResid>(a, s, total);
+    if (c.epi == kLpEpResid && c.nsplit == 1)
+      return go_lp<F16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpResid>(a, s, total);
+    if (c.epi == kLpEpCorr && c.nsplit == 1)
+      return go_lp<F16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpCorr>(a, s, total);
+  }
   // residual: N_L * N_X (both strictly lower), split or not
   if (c.amask == 2 && c.bmask == 2 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoN0 &&
       c.khi == kHiM1 && c.epi == kLpEpResid) {

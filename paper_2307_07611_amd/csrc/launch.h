@@ -26,6 +26,11 @@ hipError_t launch_leaf(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, in
 // tile set and the order in which tiles are dispatched (heaviest first).
 enum KLo { kLoZero = 0, kLoN0 = 1, kLoM0 = 2, kLoMax = 3 };   // k >= 0 | n0 | m0 | max(m0, n0)
 enum KHi { kHiK = 0, kHiM1 = 1, kHiN1 = 2 };                   // k < K | m0 + TM | n0 + TN
+// Low-precision products of lower tiles only: every tile of a tile block
+// takes the block's union range (first column of the block .. last row of the
+// block), so the block's tiles read the same panels at the same time; the
+// operands must hold zeros wherever that range leaves their triangles.
+enum { kLoBlock = 4, kHiBlock = 3 };
 enum Tiles { kAllTiles = 0, kLowerTiles = 1 };                  // all tiles | tiles with it >= jt
 enum Order {
   kColAsc = 0,   // all tiles, tile column ascending (work shrinks with the column)

@@ -75,10 +75,16 @@ int64_t gemm_lp_tiles(const GemmBatch& bt, int tiles);
 //   hi = round(scale v), lo = round(scale v - hi) (round-to-nearest-even in
 // the target type); each output is optional; "t" outputs are transposed
 // (element (i,j) at [j][i]). diag (optional) receives the unscaled diagonal.
+// strict: the slices hold the strictly lower part (zero diagonal).
 hipError_t launch_split(const double* S, int64_t lds, int64_t n, int f16, void* hi, void* lo, void* hi_t, void* lo_t,
-                        int64_t ldo, double* diag, int unit, double scale, hipStream_t s);
+                        int64_t ldo, double* diag, int unit, int strict, double scale, hipStream_t s);
 // The transposed hi slice only, from an FP32 lower-triangular matrix.
 hipError_t launch_split_f32(const float* S, int64_t lds, int64_t n, int f16, void* hi_t, int64_t ldo, double scale,
                             hipStream_t s);
+// Zeros in a band of `band` columns beside the tiles the split writes: to the
+// right of each 64-row strip's diagonal tile (right = 1, row-major lower
+// planes) or to its left (right = 0, transposed planes). Low-precision planes
+// read over block-union K ranges need these zeros.
+hipError_t launch_zero_band(void* P, int64_t ldo, int64_t n, int64_t band, int right, hipStream_t s);
 
 }  // namespace trinv

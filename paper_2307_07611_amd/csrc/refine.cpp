@@ -28,6 +28,7 @@ namespace trinv {
 namespace {
 
 constexpr int64_t kPart = 4096;
+constexpr int64_t kBand = 1280;  // > (tile block - 1) x tile width + 64
 
 int64_t lp_ld(int64_t n) { return (n + 8 + 63) / 64 * 64; }
 int64_t t_ld(int64_t hA) { return (hA + 8 + 63) / 64 * 64; }
@@ -175,6 +176,11 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   const double dn = (double)n;
 
   HIP_TRY(launch_fill_u64(w.status, ~0ull, 1, s));
+  // The residual and correction products read their operands over block-union
+  // K ranges, up to kBand columns past the tiles the splits and epilogues
+  // write: those bands must hold zeros (nothing writes them afterwards).
+  for (unsigned short* p : {w.Lhi, w.Llo, w.Xb}) HIP_TRY(launch_zero_band(p, ldp, n, kBand, 1, s));
+  for (unsigned short* p : {w.Xbt, w.Xtlo, w.Rt}) HIP_TRY(launch_zero_band(p, ldp, n, kBand, 0, s));
   // FP16 planes carry one power-of-two scale each (exact, undone through the
   // epilogues' alpha) so that the values sit in FP16's normal range; BF16 has
   // the exponent range of FP32 and uses 1. L: from max |L|; X during the
@@ -189,7 +195,8 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   }
   {  // staging: L -> hi / lo slices (row-major) and diag(L)
     ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + 4), s);
-    HIP_TRY(launch_split(L, ldl, n, f16, w.Lhi, w.Llo, nullptr, nullptr, ldp, w.dL, o.unit_diag, sL, s));
+    // strictly lower part: the diagonal enters the residual in FP64 only
+    HIP_TRY(launch_split(L, ldl, n, f16, w.Lhi, w.Llo, nullptr, nullptr, ldp, w.dL, o.unit_diag, 1, sL, s));
   }
   if (f16) {
     std::vector<double> d((size_t)n);
@@ -234,7 +241,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     }
     {
       ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + 6), s);
-      HIP_TRY(launch_split(X, ldx, n, f16, w.Xb, nullptr, w.Xbt, w.Xtlo, ldp, w.dX, 0, sX, s));
+      HIP_TRY(launch_split(X, ldx, n, f16, w.Xb, nullptr, w.Xbt, w.Xtlo, ldp, w.dX, 0, 1, sX, s));
     }
     if (resid_fp64 < 0) {
       HIP_TRY(launch_sumsq<double>(X, n, ldx, 1, 0, w.partial, kPart, w.scal + 4, s));
@@ -302,7 +309,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gr.ldrt = ldp;
     gr.tile_sq = w.tile_sq;
     gr.tile_sqx = w.tile_sqx;
-    LpConfig cr{f16, 3, 2, 2, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpResid};
+    LpConfig cr{f16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpResid};
     {
       ProfLaunch pl(f16 ? "f16_residual" : "bf16_residual", 3.0 * tri_flops(dn), dn * dn / 2 * (4 * 2 + 8 + 8 + 4 + 2), s);
       HIP_TRY(launch_gemm_lp(gr, cr, s));
@@ -353,7 +360,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gc.dX = w.dX;
     gc.R32 = w.R32;
     gc.ldr = n;
-    LpConfig cc{f16, 1, 2, 1, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpCorr};
+    LpConfig cc{f16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpCorr};
     {
       ProfLaunch pl(f16 ? "f16_correction" : "bf16_correction", tri_flops(dn) + dn * dn, dn * dn / 2 * (2 + 2 + 4 + 16), s);
       HIP_TRY(launch_gemm_lp(gc, cc, s));

@@ -31,7 +31,7 @@ template <int F16, typename TS>
 __global__ __launch_bounds__(256) void k_split(const TS* __restrict__ S, int64_t lds, int64_t n,
                                                u16* __restrict__ hi, u16* __restrict__ lo, u16* __restrict__ hi_t,
                                                u16* __restrict__ lo_t, int64_t ldo, double* __restrict__ diag,
-                                               int unit, double scale) {
+                                               int unit, int strict, double scale) {
   __shared__ u16 th[64][66];
   __shared__ u16 tl[64][66];
   const int64_t q = blockIdx.x;
@@ -48,6 +48,7 @@ __global__ __launch_bounds__(256) void k_split(const TS* __restrict__ S, int64_t
       double v = (j <= i) ? (double)S[i * lds + j] : 0.0;
       if (unit && i == j) v = 1.0;
       if (i == j && diag) diag[i] = v;
+      if (strict && i == j) v = 0.0;  // slices of the strictly lower part
       v *= scale;
       double hb;
       h = lp_bits<F16>(v, &hb);
@@ -72,26 +73,50 @@ __global__ __launch_bounds__(256) void k_split(const TS* __restrict__ S, int64_t
 
 template <typename TS>
 static hipError_t split_t(const TS* S, int64_t lds, int64_t n, int f16, void* hi, void* lo, void* hi_t, void* lo_t,
-                          int64_t ldo, double* diag, int unit, double scale, hipStream_t s) {
+                          int64_t ldo, double* diag, int unit, int strict, double scale, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t T = (n + 63) / 64, blocks = T * (T + 1) / 2;
   if (f16)
     hipLaunchKernelGGL((k_split<1, TS>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, (u16*)hi, (u16*)lo,
-                       (u16*)hi_t, (u16*)lo_t, ldo, diag, unit, scale);
+                       (u16*)hi_t, (u16*)lo_t, ldo, diag, unit, strict, scale);
   else
     hipLaunchKernelGGL((k_split<0, TS>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, (u16*)hi, (u16*)lo,
-                       (u16*)hi_t, (u16*)lo_t, ldo, diag, unit, scale);
+                       (u16*)hi_t, (u16*)lo_t, ldo, diag, unit, strict, scale);
   return hipGetLastError();
 }
 
 hipError_t launch_split(const double* S, int64_t lds, int64_t n, int f16, void* hi, void* lo, void* hi_t, void* lo_t,
-                        int64_t ldo, double* diag, int unit, double scale, hipStream_t s) {
-  return split_t<double>(S, lds, n, f16, hi, lo, hi_t, lo_t, ldo, diag, unit, scale, s);
+                        int64_t ldo, double* diag, int unit, int strict, double scale, hipStream_t s) {
+  return split_t<double>(S, lds, n, f16, hi, lo, hi_t, lo_t, ldo, diag, unit, strict, scale, s);
 }
 
 hipError_t launch_split_f32(const float* S, int64_t lds, int64_t n, int f16, void* hi_t, int64_t ldo, double scale,
                             hipStream_t s) {
-  return split_t<float>(S, lds, n, f16, nullptr, nullptr, hi_t, nullptr, ldo, nullptr, 0, scale, s);
+  return split_t<float>(S, lds, n, f16, nullptr, nullptr, hi_t, nullptr, ldo, nullptr, 0, 0, scale, s);
+}
+
+// Zeros in a band of `band` columns next to the 64 x 64 tiles the split
+// writes: for rows in 64-row strip q, columns [(q + 1) 64, (q + 1) 64 + band)
+// (right = 1, row-major lower planes) or [q 64 - band, q 64) (right = 0,
+// transposed planes), clipped to [0, ldo). One block per strip.
+__global__ __launch_bounds__(256) void k_zero_band(u16* __restrict__ P, int64_t ldo, int64_t n, int64_t band,
+                                                   int right) {
+  const int64_t q = blockIdx.x;
+  const int64_t c0 = right ? (q + 1) * 64 : q * 64 - band;
+  const int64_t lo = c0 < 0 ? 0 : c0, hi = (c0 + band < ldo) ? c0 + band : ldo;
+  if (hi <= lo) return;
+  const int64_t w = hi - lo;
+  for (int64_t r = 0; r < 64; ++r) {
+    const int64_t i = q * 64 + r;
+    if (i >= n) break;
+    for (int64_t j = threadIdx.x; j < w; j += 256) P[i * ldo + lo + j] = 0;
+  }
+}
+
+hipError_t launch_zero_band(void* P, int64_t ldo, int64_t n, int64_t band, int right, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_band, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, (u16*)P, ldo, n, band, right);
+  return hipGetLastError();
 }
 
 }  // namespace trinv
