@@ -303,12 +303,14 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<TI> a) {
             if (row == col) rv = fma(-lii, xij, 1.0);
             else rv = -(double)acc[i][j][r] - lii * xij - (double)a.Lfull[row * a.ldl + col] * a.dX[col];
             a.R32[row * a.ldr + col] = (float)rv;
-            const int64_t e = col * a.ldrt + row;
-            if (a.lp_is_f16) ((_Float16*)a.Rt)[e] = (_Float16)(float)rv;
-            else ((__bf16*)a.Rt)[e] = (__bf16)(float)rv;
+            if (a.Rt) {
+              const int64_t e = col * a.ldrt + row;
+              if (a.lp_is_f16) ((_Float16*)a.Rt)[e] = (_Float16)(float)rv;
+              else ((__bf16*)a.Rt)[e] = (__bf16)(float)rv;
+            }
             sq += rv * rv;
             sqx += xij * xij;
-          } else if (row < M && col < N) {  // above the diagonal: zero in the transposed copy
+          } else if (row < M && col < N && a.Rt) {  // above the diagonal: zero in the transposed copy
             const int64_t e = col * a.ldrt + row;
             if (a.lp_is_f16) ((_Float16*)a.Rt)[e] = (_Float16)0.f;
             else ((__bf16*)a.Rt)[e] = (__bf16)0.f;

@@ -192,6 +192,10 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   tb[1] = (const u16*)a.Bt_hi + z * a.b_bstride;
   tb[2] = NSPLIT == 3 ? (const u16*)a.A_lo + z * a.a_bstride : nullptr;
   tb[3] = NSPLIT == 3 ? (const u16*)a.Bt_lo + z * a.b_bstride : nullptr;
+  // Panel-blocked operands (block-union products): the stage of a tile is
+  // KT / 16 consecutive 8 KB blocks of its 256-row panel, copied linearly, so
+  // the LDS tile is [KT / 16][256][16] with the plane's half exchange.
+  constexpr bool PB = (KLO == kLoBlock);
   uint32_t off[S::NT][S::IPW];  // byte offsets of this lane's source chunk, stage 0
 #pragma unroll
   for (int tt = 0; tt < S::NT; ++tt) {
@@ -200,10 +204,14 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
     const int64_t r0 = isb ? n0 : m0, rmax = (isb ? N : M) - 1;
 #pragma unroll
     for (int i = 0; i < S::IPW; ++i) {
-      const int row = (wave * S::IPW + i) * S::RPI + lane / S::CPR;
-      const int chunk = (lane % S::CPR) ^ S::swz(row);
-      const int64_t grow = imin64(r0 + row, rmax);
-      off[tt][i] = (uint32_t)((grow * ld + klo + 8 * chunk) * 2);
+      if constexpr (PB) {
+        off[tt][i] = (uint32_t)((((r0 >> 8) * ld + (klo >> 4)) * 4096 + (wave * S::IPW + i) * 512 + lane * 8) * 2);
+      } else {
+        const int row = (wave * S::IPW + i) * S::RPI + lane / S::CPR;
+        const int chunk = (lane % S::CPR) ^ S::swz(row);
+        const int64_t grow = imin64(r0 + row, rmax);
+        off[tt][i] = (uint32_t)((grow * ld + klo + 8 * chunk) * 2);
+      }
     }
   }
   auto issue = [&](int buf, int64_t kstage) {  // loads of the stage starting at klo + kstage
@@ -211,7 +219,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
     lds_char* base = (lds_char*)lds + (size_t)buf * S::NT * S::TILE * 2;
 #pragma unroll
     for (int tt = 0; tt < S::NT; ++tt) {
-      const char* src = (const char*)tb[tt] + kstage * 2;
+      const char* src = (const char*)tb[tt] + (PB ? (kstage >> 4) * 4096 * 2 : kstage * 2);
 #pragma unroll
       for (int i = 0; i < S::IPW; ++i)
         __builtin_amdgcn_global_load_lds((const void*)(src + off[tt][i]),
@@ -225,8 +233,11 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   // The swizzle has a period of 16 rows, which divides 32, so it depends on
   // lane & 31 only and the block offset folds into an immediate.
   const int fsw = S::swz(lane & 31);
+  const int fpb = ((lane & 31) >> 3) & 1;  // blocked layout: half exchange of the row
   auto frag = [&](const u16* base, int tt, int ks, int blk) -> u32x4 {
     const int row = ((tt & 1) ? wn : wm) * 128 + blk * 32 + (lane & 31);
+    if constexpr (PB)
+      return *(const u32x4*)(base + tt * S::TILE + (ks >> 4) * 4096 + row * 16 + 8 * ((lane >> 5) ^ fpb));
     const int chunk = ks / 8 + (lane >> 5);
     return *(const u32x4*)(base + tt * S::TILE + row * S::KT + 8 * (chunk ^ fsw));
   };
@@ -241,9 +252,20 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
       const bool isb = tt & 1;
       const int64_t r0 = isb ? n0 : m0;
       for (int c = tid; c < CH; c += 256) {
-        const int row = c / S::CPR, p = c % S::CPR;
-        const int64_t kb = k0 + 8 * (p ^ S::swz(row));
-        u32x4* ptr = (u32x4*)(base + tt * S::TILE + row * S::KT + 8 * p);
+        int row, p;
+        int64_t kb;
+        u32x4* ptr;
+        if constexpr (PB) {  // chunk c: block c / 512, row (c / 2) % 256, half c % 2
+          row = (c >> 1) & 255;
+          p = c & 1;
+          kb = k0 + 16 * (c >> 9) + 8 * (p ^ ((row >> 3) & 1));
+          ptr = (u32x4*)(base + tt * S::TILE + 8 * c);
+        } else {
+          row = c / S::CPR;
+          p = c % S::CPR;
+          kb = k0 + 8 * (p ^ S::swz(row));
+          ptr = (u32x4*)(base + tt * S::TILE + row * S::KT + 8 * p);
+        }
         u32x4 v = *ptr;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -483,7 +505,8 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
               o[e] = to_lp<F16>((float)(rv * a.lp_scale));
             }
             if (a.Rt) {  // uniform: the FP16 path writes R in low precision in a separate pass
-              u16* dst = (u16*)a.Rt + col * a.ldrt + row0;
+              // Rt panel-blocked (row = col, k = row0 .. row0 + 3: 8 contiguous bytes)
+              u16* dst = (u16*)a.Rt + pb_index(col, row0, a.ldrt);
               if (full || (colok && row0 + 3 < M)) {
                 uint2 v;
                 v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
@@ -577,18 +600,6 @@ static hipError_t dispatch_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_
       return go_lp<F16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpResid>(a, s, total);
     if (c.epi == kLpEpCorr && c.nsplit == 1)
       return go_lp<F16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpCorr>(a, s, total);
-  }
-  // residual: N_L * N_X (both strictly lower), split or not
-  if (c.amask == 2 && c.bmask == 2 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoN0 &&
-      c.khi == kHiM1 && c.epi == kLpEpResid) {
-    if (c.nsplit == 3) return go_lp<F16, 3, 2, 2, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpResid>(a, s, total);
-    if (c.nsplit == 1) return go_lp<F16, 1, 2, 2, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpResid>(a, s, total);
-  }
-  // correction: N_X * R (N_X strictly lower, R lower)
-  if (c.amask == 2 && c.bmask == 1 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoN0 &&
-      c.khi == kHiM1 && c.epi == kLpEpCorr) {
-    if (c.nsplit == 1) return go_lp<F16, 1, 2, 1, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpCorr>(a, s, total);
-    if (c.nsplit == 3) return go_lp<F16, 3, 2, 1, kLowerTiles, kDiagDesc, kLoN0, kHiM1, kLpEpCorr>(a, s, total);
   }
   return hipErrorInvalidValue;
 }

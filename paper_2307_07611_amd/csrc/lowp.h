@@ -22,7 +22,10 @@ enum LpEpilogue {
 // All operands in element units of their own type. Low-precision operands:
 // A row-major [m][k]; B stored transposed, Bt[n][k] = B(k, n), so both are
 // k-contiguous. Every low-precision buffer must have at least 8 readable
-// padding columns past the last column a product uses.
+// padding columns past the last column a product uses. Products over
+// block-union K ranges (klo = kLoBlock) read panel-blocked planes instead, and
+// lda / ldb are then their K blocks per panel; their residual epilogue writes
+// Rt panel-blocked too (ldrt = K blocks per panel).
 struct LpGemmArgs {
   const void* A_hi;
   const void* A_lo;  // second slice (3-product split) or null
@@ -69,22 +72,50 @@ struct LpConfig {
 hipError_t launch_gemm_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_t s);
 int64_t gemm_lp_tiles(const GemmBatch& bt, int tiles);
 
+// Panel-blocked plane (the operands of the refinement products): rows in
+// panels of 256, K in blocks of 16; the 256 x 16 block of panel p and K block b
+// is 8 KB of contiguous memory at element ((p kb + b) 4096), row-major (32-byte
+// rows), with the two 16-byte halves of a row exchanged in rows whose bit 3 is
+// set. A stage of a product is then a contiguous range per operand tile, which
+// direct global -> LDS loads copy as is: the half exchange is the LDS bank
+// swizzle of the fragment reads. kb = K blocks per panel.
+__host__ __device__ inline int64_t pb_index(int64_t r, int64_t k, int64_t kb) {
+  const int64_t rr = r & 255, kk = k & 15;
+  return (((r >> 8) * kb + (k >> 4)) << 12) + (rr << 4) + ((((kk >> 3) ^ ((rr >> 3) & 1))) << 3) + (kk & 7);
+}
+// K blocks per panel for order n: the splits write whole 64-wide tiles (up
+// to the next multiple of 64), and the last stage of a product may read up to
+// 31 elements past the last column (masked in LDS, but inside the plane).
+inline int64_t pb_kblocks(int64_t n) { return (n + 63) / 64 * 4 + 2; }
+inline size_t pb_elems(int64_t n) { return (size_t)((n + 255) / 256) * (size_t)pb_kblocks(n) * 4096; }
+
+// Outputs of a split (any may be null): row-major hi / lo and transposed
+// hi_t / lo_t with leading dimension ldo; panel-blocked hi_b / lo_b (element
+// (i, j) at row i, k = j) and hi_tb / lo_tb (element (i, j) at row j, k = i)
+// with kb K blocks per panel.
+struct SplitOut {
+  unsigned short *hi, *lo, *hi_t, *lo_t;
+  int64_t ldo;
+  unsigned short *hi_b, *lo_b, *hi_tb, *lo_tb;
+  int64_t kb;
+};
+
 // Low-precision slices of a lower-triangular FP64 matrix times a power-of-two
 // scale (64 x 64 tiles of the lower triangle; elements above the diagonal are
 // written as 0 inside diagonal tiles and not at all elsewhere):
 //   hi = round(scale v), lo = round(scale v - hi) (round-to-nearest-even in
-// the target type); each output is optional; "t" outputs are transposed
-// (element (i,j) at [j][i]). diag (optional) receives the unscaled diagonal.
-// strict: the slices hold the strictly lower part (zero diagonal).
-hipError_t launch_split(const double* S, int64_t lds, int64_t n, int f16, void* hi, void* lo, void* hi_t, void* lo_t,
-                        int64_t ldo, double* diag, int unit, int strict, double scale, hipStream_t s);
-// The transposed hi slice only, from an FP32 lower-triangular matrix.
-hipError_t launch_split_f32(const float* S, int64_t lds, int64_t n, int f16, void* hi_t, int64_t ldo, double scale,
+// the target type). diag (optional) receives the unscaled diagonal. strict:
+// the slices hold the strictly lower part (zero diagonal).
+hipError_t launch_split(const double* S, int64_t lds, int64_t n, int f16, const SplitOut& o, double* diag, int unit,
+                        int strict, double scale, hipStream_t s);
+// The same from an FP32 lower-triangular matrix (no diagonal output).
+hipError_t launch_split_f32(const float* S, int64_t lds, int64_t n, int f16, const SplitOut& o, double scale,
                             hipStream_t s);
-// Zeros in a band of `band` columns beside the tiles the split writes: to the
-// right of each 64-row strip's diagonal tile (right = 1, row-major lower
-// planes) or to its left (right = 0, transposed planes). Low-precision planes
-// read over block-union K ranges need these zeros.
-hipError_t launch_zero_band(void* P, int64_t ldo, int64_t n, int64_t band, int right, hipStream_t s);
+// Zeros in a band of `band` columns (multiple of 8) beside the tiles the split
+// writes, in a panel-blocked plane: to the right of each 64-row strip's
+// diagonal tile (right = 1, planes holding a lower triangle) or to its left
+// (right = 0, transposed planes). The refinement products read their operands
+// over block-union K ranges and need these zeros.
+hipError_t launch_zero_band_pb(void* P, int64_t kb, int64_t n, int64_t band, int right, hipStream_t s);
 
 }  // namespace trinv

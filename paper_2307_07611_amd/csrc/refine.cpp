@@ -41,24 +41,33 @@ int64_t lp_t_elems(int64_t n, int64_t leaf) {
 
 struct WsRefine {
   uint64_t* status;
-  unsigned short *Lhi, *Llo, *Xb, *Xbt, *Xtlo, *Tt, *Rt;
+  // row-major planes of the forward recursion: hi(L), hi(X), hi(X)^T, T^T
+  unsigned short *Lhi, *Xb, *Xbt, *Tt;
+  // panel-blocked planes of the refinement products: A roles hi/lo(N_L) and
+  // hi(N_X); B roles hi/lo(N_X)^T and R^T
+  unsigned short *PLhi, *PLlo, *PX, *PXthi, *PXtlo, *PRt;
   float* R32;
   double *dL, *dX, *tile_sq, *tile_sqx, *partial, *scal;
-  int64_t ldp;
+  int64_t ldp, kb;
 };
 
 WsRefine carve_refine(Carve& c, int64_t n, int64_t leaf) {
   WsRefine w;
   w.ldp = lp_ld(n);
-  const size_t pl = (size_t)n * w.ldp + 512;  // one low-precision plane (+ slack for over-reads)
+  w.kb = pb_kblocks(n);
+  const size_t pl = (size_t)n * w.ldp + 512;  // one row-major plane (+ slack for over-reads)
+  const size_t pp = pb_elems(n);              // one panel-blocked plane
   w.status = c.take<uint64_t>(1);
   w.Lhi = c.take<unsigned short>(pl);
-  w.Llo = c.take<unsigned short>(pl);
   w.Xb = c.take<unsigned short>(pl);
   w.Xbt = c.take<unsigned short>(pl);
-  w.Xtlo = c.take<unsigned short>(pl);
-  w.Rt = c.take<unsigned short>(pl);
   w.Tt = c.take<unsigned short>((size_t)lp_t_elems(n, leaf) + 512);
+  w.PLhi = c.take<unsigned short>(pp);
+  w.PLlo = c.take<unsigned short>(pp);
+  w.PX = c.take<unsigned short>(pp);
+  w.PXthi = c.take<unsigned short>(pp);
+  w.PXtlo = c.take<unsigned short>(pp);
+  w.PRt = c.take<unsigned short>(pp);
   w.R32 = c.take<float>((size_t)n * n);
   w.dL = c.take<double>((size_t)n);
   w.dX = c.take<double>((size_t)n);
@@ -179,8 +188,8 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   // The residual and correction products read their operands over block-union
   // K ranges, up to kBand columns past the tiles the splits and epilogues
   // write: those bands must hold zeros (nothing writes them afterwards).
-  for (unsigned short* p : {w.Lhi, w.Llo, w.Xb}) HIP_TRY(launch_zero_band(p, ldp, n, kBand, 1, s));
-  for (unsigned short* p : {w.Xbt, w.Xtlo, w.Rt}) HIP_TRY(launch_zero_band(p, ldp, n, kBand, 0, s));
+  for (unsigned short* p : {w.PLhi, w.PLlo, w.PX}) HIP_TRY(launch_zero_band_pb(p, w.kb, n, kBand, 1, s));
+  for (unsigned short* p : {w.PXthi, w.PXtlo, w.PRt}) HIP_TRY(launch_zero_band_pb(p, w.kb, n, kBand, 0, s));
   // FP16 planes carry one power-of-two scale each (exact, undone through the
   // epilogues' alpha) so that the values sit in FP16's normal range; BF16 has
   // the exponent range of FP32 and uses 1. L: from max |L|; X during the
@@ -196,7 +205,13 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   {  // staging: L -> hi / lo slices (row-major) and diag(L)
     ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + 4), s);
     // strictly lower part: the diagonal enters the residual in FP64 only
-    HIP_TRY(launch_split(L, ldl, n, f16, w.Lhi, w.Llo, nullptr, nullptr, ldp, w.dL, o.unit_diag, 1, sL, s));
+    SplitOut so{};
+    so.hi = w.Lhi;  // row-major hi(L) for the forward products
+    so.ldo = ldp;
+    so.hi_b = w.PLhi;  // panel-blocked hi / lo for the residual
+    so.lo_b = w.PLlo;
+    so.kb = w.kb;
+    HIP_TRY(launch_split(L, ldl, n, f16, so, w.dL, o.unit_diag, 1, sL, s));
   }
   if (f16) {
     std::vector<double> d((size_t)n);
@@ -241,7 +256,12 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     }
     {
       ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + 6), s);
-      HIP_TRY(launch_split(X, ldx, n, f16, w.Xb, nullptr, w.Xbt, w.Xtlo, ldp, w.dX, 0, 1, sX, s));
+      SplitOut so{};
+      so.hi_b = w.PX;  // A role of the correction
+      so.hi_tb = w.PXthi;  // B role of the residual
+      so.lo_tb = w.PXtlo;
+      so.kb = w.kb;
+      HIP_TRY(launch_split(X, ldx, n, f16, so, w.dX, 0, 1, sX, s));
     }
     if (resid_fp64 < 0) {
       HIP_TRY(launch_sumsq<double>(X, n, ldx, 1, 0, w.partial, kPart, w.scal + 4, s));
@@ -274,8 +294,8 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       gf.dX = w.dX;
       gf.R32 = w.R32;
       gf.ldr = n;
-      gf.Rt = w.Rt;
-      gf.ldrt = ldp;
+      gf.Rt = nullptr;  // R^T for the correction is cast from R32 below
+      gf.ldrt = 0;
       gf.lp_is_f16 = f16;
       gf.tile_sq = w.tile_sq;
       gf.tile_sqx = w.tile_sqx;
@@ -288,12 +308,12 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       HIP_TRY(launch_reduce_sum(w.tile_sqx, ntf, w.scal + 1, s));
     } else {
     LpGemmArgs gr{};
-    gr.A_hi = w.Lhi;
-    gr.A_lo = w.Llo;
-    gr.lda = ldp;
-    gr.Bt_hi = w.Xbt;
-    gr.Bt_lo = w.Xtlo;
-    gr.ldb = ldp;
+    gr.A_hi = w.PLhi;
+    gr.A_lo = w.PLlo;
+    gr.lda = w.kb;
+    gr.Bt_hi = w.PXthi;
+    gr.Bt_lo = w.PXtlo;
+    gr.ldb = w.kb;
     gr.bt = bt;
     gr.alpha = 1.0 / (sL * sX);  // acc = (sL N_L)(sX N_X)
     gr.lp_scale = 1.0;
@@ -305,8 +325,8 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gr.dX = w.dX;
     gr.R32 = w.R32;
     gr.ldr = n;
-    gr.Rt = f16 ? nullptr : w.Rt;  // FP16: written below, once ||R|| is known
-    gr.ldrt = ldp;
+    gr.Rt = f16 ? nullptr : w.PRt;  // FP16: written below, once ||R|| is known
+    gr.ldrt = w.kb;
     gr.tile_sq = w.tile_sq;
     gr.tile_sqx = w.tile_sqx;
     LpConfig cr{f16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpResid};
@@ -341,17 +361,20 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     if (rho <= o.tol) return TRINV_OK;
     if (iter >= o.max_iter) return TRINV_ERR_NOT_CONVERGED;
     double sR = 1.0;
-    if (f16) {  // FP16 R for the correction's B operand, scaled by ||R||_F
-      sR = pow2_scale(std::sqrt(h[0]), 14);
+    if (f16 || resid_fp64) {  // R^T for the correction's B operand (FP16: scaled by ||R||_F)
+      if (f16) sR = pow2_scale(std::sqrt(h[0]), 14);
+      SplitOut so{};
+      so.hi_tb = w.PRt;
+      so.kb = w.kb;
       ProfLaunch pl("split", 0.0, dn * dn / 2 * (4 + 2), s);
-      HIP_TRY(launch_split_f32(w.R32, n, n, 1, w.Rt, ldp, sR, s));
+      HIP_TRY(launch_split_f32(w.R32, n, n, f16, so, sR, s));
     }
     // correction: X <- X + D_X R + N_X R
     LpGemmArgs gc{};
-    gc.A_hi = w.Xb;
-    gc.lda = ldp;
-    gc.Bt_hi = w.Rt;
-    gc.ldb = ldp;
+    gc.A_hi = w.PX;
+    gc.lda = w.kb;
+    gc.Bt_hi = w.PRt;
+    gc.ldb = w.kb;
     gc.bt = bt;
     gc.alpha = 1.0 / (sX * sR);  // acc = (sX N_X)(sR R)
     gc.lp_scale = 1.0;
