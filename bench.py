@@ -195,6 +195,26 @@ def backward_secondary(P, torch, reps):
             "backward_frac_fp32_mfma": round(fb / ms_b / 1e9 / PEAK_TFLOPS["f32"], 4), "reps": reps}
 
 
+def combrit_secondary(P, torch, Ld, reps):
+    """Top level of algorithm COMBRIT on a beta x beta block grid (FP64), on
+    the same n = 16384 matrix: effective TFLOP/s (n^3/3) and the residual."""
+    n = Ld.shape[0]
+    out = {"workload": f"COMBRIT top level, FP64, n={n} (same matrix as the headline)"}
+    for beta in (4, 8):
+        X = torch.empty_like(Ld)
+        ws = torch.empty(max(P.workspace_bytes(n, "f64", beta=beta, leaf=128), 1), dtype=torch.uint8,
+                         device=Ld.device)
+        run = lambda: P.tril_inverse(Ld, "f64", beta=beta, leaf=128, out=X, workspace=ws, blocking=False)  # noqa
+        run()
+        ms = time_events(torch, run, reps)
+        r = P.residual(Ld, X)
+        out[f"beta{beta}"] = {"ms": round(ms, 4), "tflops": round(n ** 3 / 3 / ms / 1e9, 3),
+                              "rel_residual": r["rel"]}
+        del X, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(L, seconds):
     """The oracle (column recurrence, all host cores via OpenMP) on a bounded
     sample of the same matrix: evenly spaced columns of L^-1."""
@@ -310,6 +330,10 @@ def main():
         log("backward 64 x 1024 FP32")
         out["secondary"]["backward"] = backward_secondary(P, torch, 10)
         log(f"backward: {out['secondary']['backward']['backward_ms']} ms")
+        if n == 16384:
+            log("COMBRIT beta = 4, 8 (FP64)")
+            out["secondary"]["combrit"] = combrit_secondary(P, torch, Ld, 3)
+            log(f"combrit: {out['secondary']['combrit']}")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(L, args.cpu_seconds)

@@ -97,6 +97,12 @@ typedef struct {
   int32_t blocking;  /* 1: wait for the GPU and fill *info (status, residual) */
   int32_t check;     /* 1 (with blocking): also compute the FP64 relative
                         residual of the result into info->rel_residual */
+  int32_t beta;      /* block grid of the top level, algorithm COMBRIT
+                        (Section 4.1): 0 or 2 = the binary recursion; 3..16 =
+                        beta x beta blocks of order n / beta at the top (F64 /
+                        F32, lower, n divisible by beta, ldl == ldx, else
+                        TRINV_ERR_ARG / TRINV_ERR_UNSUPPORTED), the diagonal
+                        blocks by the binary recursion */
 } trinv_opts;
 
 typedef struct {
@@ -107,8 +113,8 @@ typedef struct {
 } trinv_info;
 
 /* Fills *opts with the defaults (leaf 0, unit_diag 0, upper 0, max_iter 4,
- * tol 1e-12, blocking 0, check 0). Passing opts == NULL to any call means
- * these defaults. */
+ * tol 1e-12, blocking 0, check 0, beta 0). Passing opts == NULL to any call
+ * means these defaults. */
 void trinv_default_opts(trinv_opts *opts);
 
 /* Human-readable name of a status code (static storage). */

@@ -33,7 +33,7 @@ class ProfileEntry(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int32), ("unit_diag", ctypes.c_int32), ("upper", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("blocking", ctypes.c_int32),
-                ("check", ctypes.c_int32)]
+                ("check", ctypes.c_int32), ("beta", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

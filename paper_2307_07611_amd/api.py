@@ -37,11 +37,12 @@ def _mode_for(t: torch.Tensor, mode):
     return m
 
 
-def _opts(leaf=0, unit_diag=False, upper=False, max_iter=4, tol=1e-12, blocking=True, check=False):
+def _opts(leaf=0, unit_diag=False, upper=False, max_iter=4, tol=1e-12, blocking=True, check=False, beta=0):
     o = _lib.Opts()
     _lib.load().trinv_default_opts(ctypes.byref(o))
     o.leaf, o.unit_diag, o.upper = int(leaf), int(unit_diag), int(upper)
     o.max_iter, o.tol, o.blocking, o.check = int(max_iter), float(tol), int(blocking), int(check)
+    o.beta = int(beta)
     return o
 
 
@@ -55,8 +56,9 @@ def _info_dict(info: _lib.Info) -> dict:
 
 
 def tril_inverse(L: torch.Tensor, mode=None, *, leaf=0, unit_diag=False, upper=False, max_iter=4, tol=1e-12,
-                 blocking=True, check=False, out=None, workspace=None, return_info=False):
-    """X = L^-1 for one triangular matrix (lower; ``upper=True`` for upper)."""
+                 blocking=True, check=False, beta=0, out=None, workspace=None, return_info=False):
+    """X = L^-1 for one triangular matrix (lower; ``upper=True`` for upper).
+    ``beta`` > 2: top level of algorithm COMBRIT on a beta x beta block grid."""
     _check_dev(L)
     if L.dim() != 2 or L.shape[0] != L.shape[1] or L.stride(1) != 1:
         raise ValueError("L must be a square matrix with unit column stride")
@@ -64,7 +66,7 @@ def tril_inverse(L: torch.Tensor, mode=None, *, leaf=0, unit_diag=False, upper=F
     n = L.shape[0]
     X = out if out is not None else torch.empty((n, n), dtype=L.dtype, device=L.device)
     lib = _lib.load()
-    o = _opts(leaf, unit_diag, upper, max_iter, tol, blocking, check)
+    o = _opts(leaf, unit_diag, upper, max_iter, tol, blocking, check, beta)
     nbytes = lib.trinv_workspace_bytes(m, n, ctypes.byref(o))
     ws = workspace if workspace is not None else _workspace(nbytes, L.device)
     info = _lib.Info()

@@ -29,6 +29,9 @@ trinv_opts resolve_opts(const trinv_opts* o) {
   return r;
 }
 
+// beta > 2 selects the COMBRIT top level (0 and 2: binary recursion).
+bool combrit_beta(const trinv_opts& o) { return o.beta > 2; }
+
 int default_leaf(int mode, int64_t n) {
   if (mode == TRINV_BF16_REFINE || mode == TRINV_F16_REFINE) return n >= 4096 ? 128 : 64;
   if (mode == TRINV_F32) return n <= 512 ? 32 : 64;
@@ -286,7 +289,12 @@ size_t trinv_workspace_bytes(int mode, int64_t n, const trinv_opts* opts) {
   const int64_t leaf = o.leaf ? o.leaf : default_leaf(mode, n);
   if (mode == TRINV_BF16_REFINE || mode == TRINV_F16_REFINE) return refine_workspace_bytes(mode, n, o, leaf);
   Carve c(nullptr, 0);
-  carve_plain(c, mode, n, leaf, o.upper != 0);
+  if (combrit_beta(o) && n % o.beta == 0) {
+    c.take<uint64_t>(1);
+    c.take<char>(combrit_workspace_bytes(mode, n, o.beta, leaf));
+  } else {
+    carve_plain(c, mode, n, leaf, o.upper != 0);
+  }
   if (o.check) carve_resid(c, n);
   return c.used;
 }
@@ -309,17 +317,36 @@ int trinv_tril_inverse(int mode, int64_t n, const void* L, int64_t ldl, void* X,
   if (!valid_leaf(leaf)) return TRINV_ERR_ARG;
   const size_t es = mode == TRINV_F32 ? 4 : 8;
   if (overlaps(L, span_bytes(n, n, ldl, es), X, span_bytes(n, n, ldx, es))) return TRINV_ERR_ARG;
+  if (o.beta < 0 || o.beta == 1 || o.beta > 16) return TRINV_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
+  if ((mode == TRINV_BF16_REFINE || mode == TRINV_F16_REFINE) && combrit_beta(o)) return TRINV_ERR_UNSUPPORTED;
   if (mode == TRINV_BF16_REFINE || mode == TRINV_F16_REFINE)
     return refine_inverse(mode, n, (const double*)L, ldl, (double*)X, ldx, o, leaf, ws, ws_bytes, s, info);
 
   Carve c(ws, ws_bytes);
-  WsPlain w = carve_plain(c, mode, n, leaf, o.upper != 0);
+  WsPlain w{};
+  void* cw = nullptr;
+  size_t cw_bytes = 0;
+  if (combrit_beta(o)) {
+    if (n % o.beta != 0 || ldl != ldx) return TRINV_ERR_ARG;
+    if (o.upper) return TRINV_ERR_UNSUPPORTED;
+    w.status = c.take<uint64_t>(1);
+    cw_bytes = combrit_workspace_bytes(mode, n, o.beta, leaf);
+    cw = c.take<char>(cw_bytes);
+  } else {
+    w = carve_plain(c, mode, n, leaf, o.upper != 0);
+  }
   WsResid wr{};
   if (o.check) wr = carve_resid(c, n);
   if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
   HIP_TRY(launch_fill_u64(w.status, ~0ull, 1, s));
-  if (mode == TRINV_F64)
+  if (cw && mode == TRINV_F64)
+    HIP_TRY(combrit_t<double>(n, (const double*)L, ldl, (double*)X, o.unit_diag, o.beta, leaf, cw, cw_bytes,
+                              w.status, s));
+  else if (cw)
+    HIP_TRY(combrit_t<float>(n, (const float*)L, ldl, (float*)X, o.unit_diag, o.beta, leaf, cw, cw_bytes, w.status,
+                             s));
+  else if (mode == TRINV_F64)
     HIP_TRY(plain_inverse<double>(n, (const double*)L, ldl, (double*)X, ldx, o, leaf, w, s));
   else
     HIP_TRY(plain_inverse<float>(n, (const float*)L, ldl, (float*)X, ldx, o, leaf, w, s));

@@ -41,6 +41,7 @@ struct Level {
 
 trinv_opts resolve_opts(const trinv_opts* o);
 int default_leaf(int mode, int64_t n);
+bool combrit_beta(const trinv_opts& o);
 bool valid_leaf(int64_t b);
 std::vector<Level> levels_of(int64_t n, int64_t leaf);
 // Elements of the T workspace one matrix needs (largest level).
@@ -55,6 +56,14 @@ hipError_t run_levels(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int
 int wait_status(hipStream_t s, const uint64_t* status_dev, int64_t n, int64_t* first_bad);
 bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes);
 size_t span_bytes(int64_t rows, int64_t cols, int64_t ld, size_t es);
+
+// Top level of algorithm COMBRIT on a beta x beta block grid (combrit.cpp):
+// ld is the leading dimension of both L and X; status receives the 1-based
+// index of the first zero pivot (all ones if none).
+size_t combrit_workspace_bytes(int mode, int64_t n, int beta, int64_t leaf);
+template <typename T>
+hipError_t combrit_t(int64_t n, const T* L, int64_t ld, T* X, int unit, int beta, int64_t leaf, void* ws,
+                     size_t ws_bytes, uint64_t* status, hipStream_t s);
 
 // Mixed-precision path (refine.cpp).
 size_t refine_workspace_bytes(int mode, int64_t n, const trinv_opts& o, int64_t leaf);

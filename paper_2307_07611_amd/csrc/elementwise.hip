@@ -124,6 +124,46 @@ hipError_t launch_reduce_sum(const double* partial, int64_t count, double* out, 
   return hipGetLastError();
 }
 
+// out[0] = min over blocks b of (b * m + words[b]) for words that are set
+// (an all-ones word means no zero pivot in that block).
+__global__ void k_fold_status(const uint64_t* words, int64_t count, int64_t m, uint64_t* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t v = ~0ull;
+  for (int64_t b = 0; b < count; ++b)
+    if (words[b] != ~0ull && (uint64_t)(b * m) + words[b] < v) v = (uint64_t)(b * m) + words[b];
+  out[0] = v;
+}
+
+hipError_t launch_fold_status(const uint64_t* words, int64_t count, int64_t m, uint64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(64), 0, s, words, count, m, out);
+  return hipGetLastError();
+}
+
+// dst block b = alpha * src block b (m x m blocks at strides sstride / dstride).
+template <typename T>
+__global__ void k_block_copy(const T* src, int64_t lds, int64_t sstride, T* dst, int64_t ldd, int64_t dstride,
+                             int64_t m, int64_t nblocks, T alpha) {
+  const int64_t total = nblocks * m * m;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / (m * m), r = (e / m) % m, c = e % m;
+    dst[b * dstride + r * ldd + c] = alpha * src[b * sstride + r * lds + c];
+  }
+}
+
+template <typename T>
+hipError_t launch_block_copy(const T* src, int64_t lds, int64_t sstride, T* dst, int64_t ldd, int64_t dstride,
+                             int64_t m, int64_t nblocks, T alpha, hipStream_t s) {
+  if (m <= 0 || nblocks <= 0) return hipSuccess;
+  const int64_t total = nblocks * m * m, blocks = (total + 255) / 256;
+  hipLaunchKernelGGL((k_block_copy<T>), dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, src, lds,
+                     sstride, dst, ldd, dstride, m, nblocks, alpha);
+  return hipGetLastError();
+}
+template hipError_t launch_block_copy<double>(const double*, int64_t, int64_t, double*, int64_t, int64_t, int64_t,
+                                              int64_t, double, hipStream_t);
+template hipError_t launch_block_copy<float>(const float*, int64_t, int64_t, float*, int64_t, int64_t, int64_t,
+                                             int64_t, float, hipStream_t);
+
 __global__ void k_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     status[i] = first_bad[i] == ~0ull ? 0 : (int32_t)first_bad[i];

@@ -127,7 +127,8 @@ enum {
   kEpSubI = 16,
   kEpTileSq = 32,
   kEpLowp = 64,
-  kEpRefineResid = 128
+  kEpRefineResid = 128,
+  kEpAccum = 256  // D = alpha acc + D (read before the store)
 };
 
 template <typename TI, typename TC, int AT, int BT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EP>
@@ -349,6 +350,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs<TI> a) {
         const int64_t col = n0 + wn * 64 + j * 16 + (lane & 15);
         if (full_tile || (row < M && col < N)) {
           double v = alpha * (double)acc[i][j][r];
+          if (EP & kEpAccum) v += (double)Db[row * a.D.ld + col];
           if ((EP & kEpSubI) && row == col) v -= 1.0;
           if ((EP & kEpOutLower) && col > row) v = 0.0;
           if (EP & kEpStore) Db[row * a.D.ld + col] = (TI)v;
@@ -395,6 +397,7 @@ static int epilogue_of(const GemmArgs<TI>& a) {
   if (a.subtract_identity) ep |= kEpSubI;
   if (a.tile_sq) ep |= kEpTileSq;
   if (a.Dlp.base) ep |= kEpLowp;
+  if (a.accumulate) ep |= kEpAccum;
   if (a.refine_resid) ep = kEpRefineResid;
   return ep;
 }
@@ -422,6 +425,10 @@ hipError_t launch_gemm(const GemmArgs<TI>& a, hipStream_t s) {
     if (ep == (kEpStore | kEpMirror | kEpLowp))
       return go<TI, TC, 0, 0, 0, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kEpStore | kEpMirror | kEpLowp>(a, s, total);
   }
+  // plain accumulating product (no masks, full K): block chain sums of algorithm COMBRIT
+  if (!a.a_trans && !a.b_trans && a.amask == 0 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kColAsc &&
+      a.klo == kLoZero && a.khi == kHiK && ep == (kEpStore | kEpAccum))
+    return go<TI, TC, 0, 0, 0, 0, kAllTiles, kColAsc, kLoZero, kHiK, kEpStore | kEpAccum>(a, s, total);
   // residual check: tril(L) * X - I, norm only
   if (!a.a_trans && !a.b_trans && a.amask == 1 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kRowDesc &&
       a.klo == kLoZero && a.khi == kHiM1 && ep == (kEpSubI | kEpTileSq))

@@ -92,6 +92,7 @@ struct GemmArgs {
   int64_t ldrt;
   double* tile_sqx;
   int refine_resid;
+  int accumulate;  // D = alpha * A B + D
 };
 
 template <typename TI, typename TC>
@@ -112,6 +113,13 @@ hipError_t launch_sumsq_vec(const double* v, int64_t count, double* out, hipStre
 template <typename T>
 hipError_t launch_maxabs(const T* A, int64_t n, int64_t lda, int lower, int unit, double* partial, int64_t npartial,
                          double* out, hipStream_t s);
+// out[0] = min over blocks b of (b * m + words[b]) over the set words (all ones = unset).
+hipError_t launch_fold_status(const uint64_t* words, int64_t count, int64_t m, uint64_t* out, hipStream_t s);
+// dst block b = alpha * src block b for nblocks m x m blocks (block b of src at
+// src + b sstride, leading dimension lds; likewise dst).
+template <typename T>
+hipError_t launch_block_copy(const T* src, int64_t lds, int64_t sstride, T* dst, int64_t ldd, int64_t dstride,
+                             int64_t m, int64_t nblocks, T alpha, hipStream_t s);
 // status[i] = first_bad[i] == all ones ? 0 : first_bad[i]  (int32 per matrix).
 hipError_t launch_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count, hipStream_t s);
 // B = A^T for an n x n matrix.

@@ -62,7 +62,8 @@ def test_default_opts(lib):
 
     o = _lib.Opts()
     lib.trinv_default_opts(ctypes.byref(o))
-    assert (o.leaf, o.unit_diag, o.upper, o.max_iter, o.tol, o.blocking, o.check) == (0, 0, 0, 4, 1e-12, 0, 0)
+    assert (o.leaf, o.unit_diag, o.upper, o.max_iter, o.tol, o.blocking, o.check, o.beta) == \
+        (0, 0, 0, 4, 1e-12, 0, 0, 0)
 
 
 def test_workspace_queries(lib):
@@ -138,3 +139,29 @@ def test_batched_argument_errors_before_any_launch(lib):
                                           1 << 31, 1 << 32, ctypes.byref(o), 1 << 20, 8, None) == \
         _lib.ERR_WORKSPACE
     assert lib.trinv_batched_workspace_bytes(_lib.F32, 3, n.ctypes.data, ctypes.byref(o)) >= 3 * 4 + 4
+
+
+def test_combrit_argument_errors_before_any_launch(lib):
+    from paper_2307_07611_amd import _lib
+
+    def call(mode, n, ldl, ldx, **kw):
+        o = _lib.Opts()
+        lib.trinv_default_opts(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return lib.trinv_tril_inverse(mode, n, 1 << 30, ldl, 1 << 34, ldx, ctypes.byref(o), None, 0, None, None)
+
+    assert call(_lib.F64, 1000, 1000, 1000, beta=1) == _lib.ERR_ARG
+    assert call(_lib.F64, 1000, 1000, 1000, beta=-2) == _lib.ERR_ARG
+    assert call(_lib.F64, 1088, 1088, 1088, beta=17) == _lib.ERR_ARG
+    assert call(_lib.F64, 1000, 1000, 1000, beta=3) == _lib.ERR_ARG        # 1000 % 3 != 0
+    assert call(_lib.F64, 1024, 1024, 1030, beta=4) == _lib.ERR_ARG        # ldl != ldx
+    assert call(_lib.F64, 1024, 1024, 1024, beta=4, upper=1) == _lib.ERR_UNSUPPORTED
+    assert call(_lib.BF16_REFINE, 1024, 1024, 1024, beta=4) == _lib.ERR_UNSUPPORTED
+    assert call(_lib.F64, 1024, 1024, 1024, beta=4) == _lib.ERR_WORKSPACE  # valid, but no workspace
+    w2 = lib.trinv_workspace_bytes(_lib.F64, 1024, None)
+    o = _lib.Opts()
+    lib.trinv_default_opts(ctypes.byref(o))
+    o.beta = 4
+    w4 = lib.trinv_workspace_bytes(_lib.F64, 1024, ctypes.byref(o))
+    assert w4 >= 2 * 1024 * 1024 * 8 > w2  # B and its inverse, n x n each
