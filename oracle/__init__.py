@@ -24,6 +24,12 @@ What each function follows, and what pins it (tests/test_oracle_pins.py):
   2^(b-a-1) (Proposition corrTranlation) and the H(1,5) listing, by exact
   rational arithmetic on integer inputs, and by agreement with the
   recurrence (an independent derivation).
+* ``crout_lu`` / ``skul`` -- the Crout factorization steps of SKUL (Section 5;
+  L lower, U unit upper, no pivoting), then ``factored_inverse``. Pinned by
+  the printed 5x5 example of Section 6 (L, U, S, K), exact recovery of integer
+  factors with unit-modulus pivots, agreement with scipy's LU (partial
+  pivoting is the identity for column diagonally dominant matrices) after the
+  Crout rescaling, L U = A, and zero pivots reported by index.
 * ``factored_inverse`` -- the output statement of SKUL (Section 5): S K =
   A^{-1} with S = U^{-1}, K = L^{-1}. Pinned by the printed 5x5 example of
   Section 6 (L, U, S, K to four decimals) and by A * Ainv = I.
@@ -67,6 +73,8 @@ def _load():
     lib.oracle_chain_sum_inverse.restype = _i64
     lib.oracle_chain_count.argtypes = [_i64, _i64]
     lib.oracle_chain_count.restype = _i64
+    lib.oracle_crout_lu.argtypes = [_i64, _dp, _i64, _dp, _dp]
+    lib.oracle_crout_lu.restype = _i64
     lib.oracle_factored_inverse.argtypes = [_i64, _dp, _i64, _i32, _dp, _i64, _i32, _dp, _dp, _dp]
     lib.oracle_factored_inverse.restype = _i64
     lib.oracle_tril_inverse_backward.argtypes = [_i64, _dp, _i64, _dp, _i64, _dp]
@@ -154,6 +162,27 @@ def factored_inverse(L, U, l_unit: bool = False, u_unit: bool = False, want_ainv
     if bad:
         raise SingularMatrix(int(abs(bad)))
     return Linv, Uinv, Ainv
+
+
+def crout_lu(A):
+    """(L, U) with A = L U, L lower, U unit upper, no pivoting (the
+    factorization steps of algorithm SKUL)."""
+    A = _f64(A)
+    n = A.shape[0]
+    L = np.empty((n, n))
+    U = np.empty((n, n))
+    bad = _load().oracle_crout_lu(n, _p(A), n, _p(L), _p(U))
+    if bad:
+        raise SingularMatrix(int(bad))
+    return L, U
+
+
+def skul(A, want_ainv: bool = True):
+    """Algorithm SKUL's outputs (L, U, S, K, Ainv): L U = A, S = U^{-1},
+    K = L^{-1}, Ainv = S K (None if not wanted)."""
+    L, U = crout_lu(A)
+    K, S, Ainv = factored_inverse(L, U, l_unit=False, u_unit=True, want_ainv=want_ainv)
+    return L, U, S, K, Ainv
 
 
 def tril_inverse_backward(L, G) -> np.ndarray:

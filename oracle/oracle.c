@@ -165,6 +165,38 @@ ORACLE_API int64_t oracle_chain_count(int64_t a, int64_t b) {
 }
 
 /*
+ * Crout decomposition without pivoting, the factorization part of algorithm
+ * SKUL (Section 5): A = L U with L lower triangular (general diagonal) and U
+ * unit upper triangular, formed row by row as the algorithm does: row i of L
+ * (columns 1..i), then row i of U (columns i+1..n):
+ *   L(i, j) = A(i, j) - sum_{k<j} L(i, k) U(k, j)               (j <= i)
+ *   U(i, j) = (A(i, j) - sum_{k<i} L(i, k) U(k, j)) / L(i, i)    (j > i)
+ * L and U are n x n row-major with leading dimension n, zero outside their
+ * triangles. Returns 0, or the 1-based index of the first zero L(i, i).
+ */
+ORACLE_API int64_t oracle_crout_lu(int64_t n, const double *A, int64_t lda, double *L, double *U) {
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      L[i * n + j] = 0.0;
+      U[i * n + j] = (i == j) ? 1.0 : 0.0;
+    }
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = 0; j <= i; ++j) {
+      double s = A[i * lda + j];
+      for (int64_t k = 0; k < j; ++k) s -= L[i * n + k] * U[k * n + j];
+      L[i * n + j] = s;
+    }
+    if (L[i * n + i] == 0.0) return i + 1;
+    for (int64_t j = i + 1; j < n; ++j) {
+      double s = A[i * lda + j];
+      for (int64_t k = 0; k < i; ++k) s -= L[i * n + k] * U[k * n + j];
+      U[i * n + j] = s / L[i * n + i];
+    }
+  }
+  return 0;
+}
+
+/*
  * Factored inverse (Section 5, SKUL: from L U = A, S K = A^{-1} with
  * S = U^{-1}, K = L^{-1}). Linv = L^{-1}; Uinv = U^{-1} obtained as the
  * transpose of (U^T)^{-1}, U^T being lower; Ainv = Uinv * Linv by the plain

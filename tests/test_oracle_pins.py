@@ -355,3 +355,63 @@ def test_backward_linear_in_g_and_rows():
     rows = [0, 5, 23]
     np.testing.assert_array_equal(oracle.tril_inverse_backward_rows(L, G1, rows),
                                   oracle.tril_inverse_backward(L, G1)[rows])
+
+
+# ---------------------------------------------------------------- SKUL factorization
+
+
+def test_crout_printed_example(golden):
+    """Section 6: the Crout factors of the printed A are the printed L and U
+    (four decimals), and the whole SKUL output reproduces the printed S, K."""
+    g = golden("skul_5x5.txt")
+    L, U, S, K, Ainv = oracle.skul(g["A"])
+    np.testing.assert_allclose(L, g["L"], atol=1.5e-4)
+    np.testing.assert_allclose(U, g["U"], atol=1.5e-4)
+    np.testing.assert_allclose(S, g["S"], atol=1.5e-4)
+    np.testing.assert_allclose(K, g["K"], atol=1.5e-4)
+    np.testing.assert_allclose(g["A"] @ Ainv, np.eye(5), atol=1e-12)
+
+
+def test_crout_integer_factors_exact():
+    """A = L0 U0 with integer L0 (diagonal +-1) and integer unit-upper U0:
+    every step of the recurrence is exact, so the factors come back bitwise."""
+    rng = np.random.default_rng(11)
+    n = 12
+    L0 = np.tril(rng.integers(-3, 4, (n, n)), -1).astype(float) + np.diag(rng.choice([-1.0, 1.0], n))
+    U0 = np.triu(rng.integers(-3, 4, (n, n)), 1).astype(float) + np.eye(n)
+    L, U = oracle.crout_lu(L0 @ U0)
+    np.testing.assert_array_equal(L, L0)
+    np.testing.assert_array_equal(U, U0)
+
+
+def test_crout_matches_scipy_lu():
+    """For a column diagonally dominant matrix partial pivoting never swaps, so
+    scipy's A = P L1 U1 (unit lower L1) has P = I, and the Crout factors are
+    L = L1 diag(U1), U = diag(U1)^{-1} U1."""
+    import scipy.linalg as sl
+
+    rng = np.random.default_rng(3)
+    n = 40
+    A = rng.uniform(-1, 1, (n, n))
+    A[np.arange(n), np.arange(n)] = np.abs(A).sum(axis=0) + 1.0
+    P, L1, U1 = sl.lu(A)
+    np.testing.assert_array_equal(P, np.eye(n))
+    d = np.diag(U1)
+    L, U = oracle.crout_lu(A)
+    np.testing.assert_allclose(L, L1 * d[None, :], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(U, U1 / d[:, None], rtol=1e-12, atol=1e-13)
+
+
+def test_crout_invariants_and_zero_pivot():
+    rng = np.random.default_rng(4)
+    n = 60
+    A = rng.uniform(-1, 1, (n, n)) + n * np.eye(n)
+    L, U = oracle.crout_lu(A)
+    assert np.all(np.triu(L, 1) == 0) and np.all(np.tril(U, -1) == 0) and np.all(np.diag(U) == 1.0)
+    np.testing.assert_allclose(L @ U, A, rtol=0, atol=1e-12 * np.abs(A).max())
+    with pytest.raises(oracle.SingularMatrix) as e:
+        oracle.crout_lu(np.array([[0.0, 1.0], [1.0, 1.0]]))
+    assert e.value.index == 1
+    with pytest.raises(oracle.SingularMatrix) as e:  # second pivot 1 - 1 * 1 = 0
+        oracle.crout_lu(np.array([[1.0, 1.0, 0.0], [1.0, 1.0, 2.0], [0.0, 3.0, 1.0]]))
+    assert e.value.index == 2
