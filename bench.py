@@ -215,6 +215,23 @@ def combrit_secondary(P, torch, Ld, reps):
     return out
 
 
+def skul_secondary(P, torch, reps):
+    """Algorithm SKUL at n = 4096, FP64: Crout factorization plus S = U^-1,
+    K = L^-1 and Ainv = S K; effective rate over 2 n^3 flops (2n^3/3 for the
+    factorization, n^3/3 per triangular inverse, 2n^3/3 for S K)."""
+    import synth
+
+    n = 4096
+    A = torch.from_numpy(synth.diag_dominant(n, 77)).cuda()
+    P.skul(A)
+    ms = time_events(torch, lambda: P.skul(A, blocking=False), reps)
+    L, U, S, K, Ainv = P.skul(A)
+    lu = float(torch.linalg.norm(L @ U - A) / torch.linalg.norm(A))
+    return {"workload": f"SKUL: Crout A = L U with S = U^-1, K = L^-1, Ainv = S K; FP64 n={n}, diagonally dominant",
+            "ms": round(ms, 3), "tflops_2n3": round(2.0 * n ** 3 / ms / 1e9, 3), "rel_lu_residual": lu,
+            "reps": reps}
+
+
 def cpu_baseline(L, seconds):
     """The oracle (column recurrence, all host cores via OpenMP) on a bounded
     sample of the same matrix: evenly spaced columns of L^-1."""
@@ -330,6 +347,9 @@ def main():
         log("backward 64 x 1024 FP32")
         out["secondary"]["backward"] = backward_secondary(P, torch, 10)
         log(f"backward: {out['secondary']['backward']['backward_ms']} ms")
+        log("SKUL n=4096 FP64")
+        out["secondary"]["skul"] = skul_secondary(P, torch, 3)
+        log(f"skul: {out['secondary']['skul']}")
         if n == 16384:
             log("COMBRIT beta = 4, 8 (FP64)")
             out["secondary"]["combrit"] = combrit_secondary(P, torch, Ld, 3)

@@ -202,6 +202,24 @@ int trinv_factored_inverse(int mode, int64_t n, const void *L, int32_t l_unit, c
                            void *ws, size_t ws_bytes, trinv_stream_t stream, trinv_info *info);
 
 /*
+ * Algorithm SKUL (Section 5): the Crout factorization A = L U (L lower with
+ * general diagonal, U unit upper; no pivoting, so A must admit it, e.g. be
+ * diagonally dominant or symmetric positive definite) together with
+ * S = U^-1 and K = L^-1, so that S K = A^-1; optionally Ainv = S K.
+ * mode: TRINV_F64 or TRINV_F32. A: device n x n row-major (leading dimension
+ * n), read only; L, U, S, K (and Ainv if not NULL): device n x n outputs,
+ * written in full, none overlapping A or each other (else TRINV_ERR_ARG).
+ * opts: leaf (the triangular inverses), blocking; upper / unit_diag / beta > 2
+ * give TRINV_ERR_UNSUPPORTED. ws: trinv_skul_workspace_bytes bytes (holds a
+ * working copy of A). A zero pivot L(i, i) makes the outputs non-finite and,
+ * with blocking, returns TRINV_ERR_SINGULAR with info->first_bad_index = i
+ * (1-based). info: nullable.
+ */
+size_t trinv_skul_workspace_bytes(int mode, int64_t n, const trinv_opts *opts);
+int trinv_skul(int mode, int64_t n, const void *A, void *L, void *U, void *S, void *K, void *Ainv,
+               const trinv_opts *opts, void *ws, size_t ws_bytes, trinv_stream_t stream, trinv_info *info);
+
+/*
  * Measurement helper (not part of the method): FP64 relative residual of a
  * candidate inverse, computed on the GPU with FP64 MFMA products:
  *   out_host[0] = ||L X - I||_F, [1] = ||tril(L)||_F, [2] = ||X||_F.

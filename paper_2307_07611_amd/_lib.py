@@ -22,6 +22,7 @@ EXPORTS = [
     "trinv_batched_workspace_bytes", "trinv_tril_inverse_batched", "trinv_backward_workspace_bytes",
     "trinv_tril_inverse_backward", "trinv_factored_workspace_bytes", "trinv_factored_inverse",
     "trinv_residual_workspace_bytes", "trinv_residual", "trinv_profile_enable", "trinv_profile_read",
+    "trinv_skul_workspace_bytes", "trinv_skul",
 ]
 
 
@@ -80,6 +81,11 @@ def load():
     lib.trinv_factored_inverse.argtypes = [ctypes.c_int, _i64, _vp, _i32, _vp, _i32, _vp, _vp, _vp,
                                            ctypes.POINTER(Opts), _vp, _sz, _vp, ctypes.POINTER(Info)]
     lib.trinv_factored_inverse.restype = ctypes.c_int
+    lib.trinv_skul_workspace_bytes.argtypes = [ctypes.c_int, _i64, ctypes.POINTER(Opts)]
+    lib.trinv_skul_workspace_bytes.restype = _sz
+    lib.trinv_skul.argtypes = [ctypes.c_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Opts), _vp, _sz,
+                               _vp, ctypes.POINTER(Info)]
+    lib.trinv_skul.restype = ctypes.c_int
     lib.trinv_residual_workspace_bytes.argtypes = [ctypes.c_int, _i64]
     lib.trinv_residual_workspace_bytes.restype = _sz
     lib.trinv_residual.argtypes = [ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp,

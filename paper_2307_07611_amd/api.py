@@ -177,6 +177,27 @@ def tril_inverse_batched(L_packed: torch.Tensor, sizes, offsets=None, mode=None,
     return X, status
 
 
+def skul(A: torch.Tensor, *, want_ainv=True, leaf=0, blocking=True):
+    """Algorithm SKUL: (L, U, S, K, Ainv) with A = L U (Crout, U unit upper, no
+    pivoting), S = U^-1, K = L^-1 and Ainv = S K (None if not wanted)."""
+    _check_dev(A)
+    A = A.contiguous()
+    m = _mode_for(A, None)
+    n = A.shape[0]
+    L, U, S, K = (torch.empty_like(A) for _ in range(4))
+    Ainv = torch.empty_like(A) if want_ainv else None
+    lib = _lib.load()
+    o = _opts(leaf=leaf, blocking=blocking)
+    ws = _workspace(lib.trinv_skul_workspace_bytes(m, n, ctypes.byref(o)), A.device)
+    info = _lib.Info()
+    st = lib.trinv_skul(m, n, A.data_ptr(), L.data_ptr(), U.data_ptr(), S.data_ptr(), K.data_ptr(),
+                        Ainv.data_ptr() if want_ainv else None, ctypes.byref(o), ws.data_ptr(), ws.numel(), _stream(),
+                        ctypes.byref(info))
+    if st != _lib.OK:
+        raise _lib.TrinvError(st, "trinv_skul", _info_dict(info))
+    return L, U, S, K, Ainv
+
+
 class BatchedGraph:
     """A fixed batch layout with static device buffers whose inversion is
     captured once in a graph (``torch.cuda.CUDAGraph``) and replayed.

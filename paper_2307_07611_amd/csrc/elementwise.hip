@@ -124,6 +124,20 @@ hipError_t launch_reduce_sum(const double* partial, int64_t count, double* out, 
   return hipGetLastError();
 }
 
+__global__ void k_zero_u32(uint32_t* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t count = (int64_t)(bytes / 4);
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = (count + 255) / 256;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, (uint32_t*)p,
+                     count);
+  return hipGetLastError();
+}
+
 // out[0] = min over blocks b of (b * m + words[b]) for words that are set
 // (an all-ones word means no zero pivot in that block).
 __global__ void k_fold_status(const uint64_t* words, int64_t count, int64_t m, uint64_t* out) {

@@ -425,7 +425,15 @@ hipError_t launch_gemm(const GemmArgs<TI>& a, hipStream_t s) {
     if (ep == (kEpStore | kEpMirror | kEpLowp))
       return go<TI, TC, 0, 0, 0, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kEpStore | kEpMirror | kEpLowp>(a, s, total);
   }
-  // plain accumulating product (no masks, full K): block chain sums of algorithm COMBRIT
+  // SKUL L panel: W * U_kk^-1 (B unit upper: k <= column)
+  if (!a.a_trans && !a.b_trans && a.amask == 0 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kColAsc &&
+      a.klo == kLoZero && a.khi == kHiN1 && ep == kEpStore)
+    return go<TI, TC, 0, 0, 0, 0, kAllTiles, kColAsc, kLoZero, kHiN1, kEpStore>(a, s, total);
+  // SKUL U panel: L_kk^-1 * W (A lower: k <= row), store only
+  if (!a.a_trans && !a.b_trans && a.amask == 0 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kRowDesc &&
+      a.klo == kLoZero && a.khi == kHiM1 && ep == kEpStore)
+    return go<TI, TC, 0, 0, 0, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kEpStore>(a, s, total);
+  // plain accumulating product (no masks, full K): block chain sums of algorithm COMBRIT, SKUL trailing update
   if (!a.a_trans && !a.b_trans && a.amask == 0 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kColAsc &&
       a.klo == kLoZero && a.khi == kHiK && ep == (kEpStore | kEpAccum))
     return go<TI, TC, 0, 0, 0, 0, kAllTiles, kColAsc, kLoZero, kHiK, kEpStore | kEpAccum>(a, s, total);

@@ -113,6 +113,14 @@ hipError_t launch_sumsq_vec(const double* v, int64_t count, double* out, hipStre
 template <typename T>
 hipError_t launch_maxabs(const T* A, int64_t n, int64_t lda, int lower, int unit, double* partial, int64_t npartial,
                          double* out, hipStream_t s);
+// Diagonal-block step of the blocked Crout factorization (skul.hip): factors
+// W[0:nb, 0:nb] (nb <= 128) into the L block (lower) and the U block (unit
+// upper) at L / U (leading dimension ld); zero pivots -> *bad (row0 + p + 1).
+template <typename T>
+hipError_t launch_crout_diag(const T* W, int64_t ldw, int nb, T* L, T* U, int64_t ld, int64_t row0, uint64_t* bad,
+                             hipStream_t s);
+// Zero bytes [p, p + bytes) (a multiple of 4) with a kernel (no memset node).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // out[0] = min over blocks b of (b * m + words[b]) over the set words (all ones = unset).
 hipError_t launch_fold_status(const uint64_t* words, int64_t count, int64_t m, uint64_t* out, hipStream_t s);
 // dst block b = alpha * src block b for nblocks m x m blocks (block b of src at

@@ -154,3 +154,18 @@ def integer_unit_lower(n: int, seed: int, lo: int = -3, hi: int = 3) -> np.ndarr
     out = np.tril(vals.astype(np.float64), -1)
     out[np.arange(n), np.arange(n)] = 1.0
     return out
+
+
+def diag_dominant(n: int, seed: int, dtype=np.float64) -> np.ndarray:
+    """Dense ``n x n`` general matrix with the distribution of the triangular
+    generator on both sides of the diagonal: off-diagonal ``(2u - 1) / n``
+    (counter ``i n + j``), diagonal ``1 + u`` (counter ``i n + i``), positive.
+    Strictly diagonally dominant, so it has a Crout factorization without
+    pivoting."""
+    k = np.arange(n * n, dtype=np.uint64)
+    u = uniform01(seed, k).reshape(n, n)
+    A = (2.0 * u - 1.0) / n
+    idx = np.arange(n)
+    A[idx, idx] = 1.0 + u[idx, idx]
+    return A.astype(dtype)
+
