@@ -115,10 +115,11 @@ hipError_t launch_maxabs(const T* A, int64_t n, int64_t lda, int lower, int unit
                          double* out, hipStream_t s);
 // Diagonal-block step of the blocked Crout factorization (skul.hip): factors
 // W[0:nb, 0:nb] (nb <= 128) into the L block (lower) and the U block (unit
-// upper) at L / U (leading dimension ld); zero pivots -> *bad (row0 + p + 1).
+// upper) at L / U (leading dimension ld) and writes their inverses K = L^-1,
+// S = U^-1 at K / S (leading dimension ldk); zero pivots -> *bad (row0 + p + 1).
 template <typename T>
-hipError_t launch_crout_diag(const T* W, int64_t ldw, int nb, T* L, T* U, int64_t ld, int64_t row0, uint64_t* bad,
-                             hipStream_t s);
+hipError_t launch_crout_diag(const T* W, int64_t ldw, int nb, T* L, T* U, int64_t ld, T* K, T* S, int64_t ldk,
+                             int64_t row0, uint64_t* bad, hipStream_t s);
 // Zero bytes [p, p + bytes) (a multiple of 4) with a kernel (no memset node).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // out[0] = min over blocks b of (b * m + words[b]) over the set words (all ones = unset).

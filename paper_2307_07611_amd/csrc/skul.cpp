@@ -2,16 +2,16 @@
 // pivoting) together with S = U^-1 and K = L^-1, so that S K = A^-1.
 //
 // Blocked, right-looking, on a working copy W of A, in steps of nb = 128:
-//   1. the diagonal block W_kk is factored in one workgroup (L_kk, U_kk);
-//   2. its inverses K_kk = L_kk^-1 and S_kk = U_kk^-1 come from the leaf
-//      kernel (column recurrence CRIT; U_kk through its transpose);
-//   3. the panels follow from them on MFMA: L_ik = W_ik S_kk (i > k) and
+//   1. the diagonal block W_kk is factored in one workgroup, which grows its
+//      inverses K_kk = L_kk^-1 and S_kk = U_kk^-1 in the same pass over the
+//      pivots (the fused recurrences of SKUL);
+//   2. the panels follow from them on MFMA: L_ik = W_ik S_kk (i > k) and
 //      U_kj = K_kk W_kj (j > k);
-//   4. the trailing block is updated: W_ij -= L_ik U_kj.
-// The paper interleaves CRIT with the Crout loop row by row; here the
-// diagonal-block inverses feed the panels, and the full K, S (and optionally
-// A^-1 = S K) are formed by the recursive engine once L and U are complete
-// (trinv_factored_inverse).
+//   3. the trailing block is updated: W_ij -= L_ik U_kj.
+// The paper grows K and S over the whole matrix beside the Crout loop; here
+// only the diagonal-block inverses are grown that way (they feed the panels),
+// and the full K, S (and optionally A^-1 = S K) are formed by the recursive
+// engine once L and U are complete (trinv_factored_inverse).
 #include <algorithm>
 
 #include "api_internal.h"
@@ -24,8 +24,8 @@ namespace {
 constexpr int64_t kNb = 128;
 
 struct WsSkul {
-  uint64_t *status, *leaf_status;
-  void *W, *Kb, *Sb, *T1, *T2, *fws;
+  uint64_t* status;
+  void *W, *Kb, *Sb, *fws;
   size_t fws_bytes;
 };
 
@@ -33,9 +33,8 @@ WsSkul carve_skul(Carve& c, int mode, int64_t n, const trinv_opts& o) {
   WsSkul w;
   const size_t es = mode == TRINV_F32 ? 4 : 8;
   w.status = c.take<uint64_t>(1);
-  w.leaf_status = c.take<uint64_t>(1);
   w.W = c.take<char>(es * (size_t)n * n);
-  for (void** p : {&w.Kb, &w.Sb, &w.T1, &w.T2}) *p = c.take<char>(es * (size_t)kNb * kNb);
+  for (void** p : {&w.Kb, &w.Sb}) *p = c.take<char>(es * (size_t)kNb * kNb);
   w.fws_bytes = trinv_factored_workspace_bytes(mode, n, &o);
   w.fws = c.take<char>(w.fws_bytes);
   return w;
@@ -44,7 +43,7 @@ WsSkul carve_skul(Carve& c, int mode, int64_t n, const trinv_opts& o) {
 template <typename T>
 hipError_t skul_lu(int64_t n, const T* A, T* L, T* U, const WsSkul& w, hipStream_t s) {
   T* W = (T*)w.W;
-  T *Kb = (T*)w.Kb, *Sb = (T*)w.Sb, *T1 = (T*)w.T1, *T2 = (T*)w.T2;
+  T *Kb = (T*)w.Kb, *Sb = (T*)w.Sb;
   hipError_t e;
   if ((e = launch_block_copy<T>(A, n, 0, W, n, 0, n, 1, T(1), s)) != hipSuccess) return e;
   if ((e = launch_zero(L, sizeof(T) * (size_t)n * n, s)) != hipSuccess) return e;
@@ -55,21 +54,12 @@ hipError_t skul_lu(int64_t n, const T* A, T* L, T* U, const WsSkul& w, hipStream
     const int64_t b = std::min(kNb, n - k0), r1 = k0 + b, rest = n - r1;
     {
       snprintf(cls, sizeof(cls), "%s_skul_diag", pre);
-      ProfLaunch pl(cls, 2.0 * b * b * b / 3.0, sizeof(T) * 3.0 * b * b, s);
-      if ((e = launch_crout_diag<T>(W + k0 * n + k0, n, (int)b, L + k0 * n + k0, U + k0 * n + k0, n, k0, w.status,
-                                    s)) != hipSuccess)
+      ProfLaunch pl(cls, 4.0 * b * b * b / 3.0, sizeof(T) * 5.0 * b * b, s);
+      if ((e = launch_crout_diag<T>(W + k0 * n + k0, n, (int)b, L + k0 * n + k0, U + k0 * n + k0, n, Kb, Sb, kNb, k0,
+                                    w.status, s)) != hipSuccess)
         return e;
     }
     if (rest == 0) break;
-    // K_kk = L_kk^-1, S_kk = U_kk^-1 (via (U_kk^T)^-1)
-    if ((e = launch_leaf<T>(b, L + k0 * n + k0, n, Kb, kNb, 0, 1, (int)kNb, 0, nullptr, nullptr, 0, 0, 1.0,
-                            w.leaf_status, 0, s)) != hipSuccess)
-      return e;
-    if ((e = launch_transpose<T>(U + k0 * n + k0, n, T1, kNb, b, s)) != hipSuccess) return e;
-    if ((e = launch_leaf<T>(b, T1, kNb, T2, kNb, 0, 1, (int)kNb, 1, nullptr, nullptr, 0, 0, 1.0, w.leaf_status, 0,
-                            s)) != hipSuccess)
-      return e;
-    if ((e = launch_transpose<T>(T2, kNb, Sb, kNb, b, s)) != hipSuccess) return e;
     const double fb = (double)b, fr = (double)rest;
     {  // L panel: L[r1:, k0:r1] = W[r1:, k0:r1] S_kk
       GemmArgs<T> g{};
@@ -161,7 +151,6 @@ extern "C" int trinv_skul(int mode, int64_t n, const void* A, void* L, void* U, 
   if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(launch_fill_u64(w.status, ~0ull, 1, s));
-  HIP_TRY(launch_fill_u64(w.leaf_status, ~0ull, 1, s));
   if (mode == TRINV_F64)
     HIP_TRY(skul_lu<double>(n, (const double*)A, (double*)L, (double*)U, w, s));
   else
