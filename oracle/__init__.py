@@ -33,6 +33,22 @@ What each function follows, and what pins it (tests/test_oracle_pins.py):
 * ``factored_inverse`` -- the output statement of SKUL (Section 5): S K =
   A^{-1} with S = U^{-1}, K = L^{-1}. Pinned by the printed 5x5 example of
   Section 6 (L, U, S, K to four decimals) and by A * Ainv = I.
+* ``sqr`` -- algorithm SQR (Section 5): modified Gram-Schmidt with S = R^{-1}
+  grown column by column (the column of S uses R(j, j) of the same column),
+  S = D S' at the end. Pinned by the printed 5x5 example of Section 6 (Q, R,
+  S, Q^T to four decimals), agreement with numpy's Householder QR after the
+  sign normalisation R(j, j) > 0, exact Q = I, R = A for an upper triangular
+  input with positive diagonal, Q^T Q = I, S R = I, S Q^T A = I, and a zero
+  column reported by index.
+* ``inverse`` -- the textbook definition of A^{-1} (Gauss-Jordan with partial
+  pivoting). Pinned by numpy's LAPACK inverse, the 2x2 closed form, exact
+  inverses of permutation and diagonal power-of-two matrices, A X = I and a
+  singular input reported by column.
+* ``brsi`` / ``brsi_split`` -- BRSI with gamma = 2 (Section 5, Steps of BRSI
+  and the gamma = 2 derivation). Pinned by agreement with ``inverse`` (odd
+  and even orders, several recursion depths), the block upper triangular case
+  (A21 = 0 gives X21 = 0 exactly and the triangular blocks), the 2x2 closed
+  form, and the factorization A = U0 U1 L of the Steps.
 * ``tril_inverse_backward`` -- grad = -tril(X^T G X^T), derived from
   dX = -X dL X (not in the paper). Pinned by FP64 central finite differences
   at n = 16, the 1x1 and 2x2 closed forms, and linearity in G.
@@ -85,6 +101,10 @@ def _load():
     lib.oracle_residuals.restype = None
     lib.oracle_residual_columns.argtypes = [_i64, _dp, _i64, _dp, _i64, _lp, _i64, _dp]
     lib.oracle_residual_columns.restype = None
+    lib.oracle_sqr.argtypes = [_i64, _dp, _i64, _dp, _dp, _dp]
+    lib.oracle_sqr.restype = _i64
+    lib.oracle_inverse.argtypes = [_i64, _dp, _i64, _dp]
+    lib.oracle_inverse.restype = _i64
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = _i32
     _lib = lib
@@ -183,6 +203,86 @@ def skul(A, want_ainv: bool = True):
     L, U = crout_lu(A)
     K, S, Ainv = factored_inverse(L, U, l_unit=False, u_unit=True, want_ainv=want_ainv)
     return L, U, S, K, Ainv
+
+
+def sqr(A, want_ainv: bool = True):
+    """Algorithm SQR's outputs (Q, R, S, Ainv): modified Gram-Schmidt
+    A = Q R with S = R^{-1} grown column by column, Ainv = S Q^T (a plain
+    matrix product; None if not wanted)."""
+    A = _f64(A)
+    n = A.shape[0]
+    Q = np.empty((n, n))
+    R = np.empty((n, n))
+    S = np.empty((n, n))
+    bad = _load().oracle_sqr(n, _p(A), n, _p(Q), _p(R), _p(S))
+    if bad:
+        raise SingularMatrix(int(bad))
+    return Q, R, S, (S @ Q.T if want_ainv else None)
+
+
+def inverse(A) -> np.ndarray:
+    """A^{-1} by Gauss-Jordan elimination with partial pivoting."""
+    A = _f64(A)
+    n = A.shape[0]
+    X = np.empty((n, n))
+    bad = _load().oracle_inverse(n, _p(A), n, _p(X))
+    if bad:
+        raise SingularMatrix(int(bad))
+    return X
+
+
+def brsi_split(A):
+    """One pass of the gamma = 2 split of BRSI (Section 5, Steps of BRSI and
+    the gamma = 2 derivation), for A with invertible diagonal blocks
+    (h = n // 2): U0 is the block upper part of A, S = U0^{-1} with blocks
+    S11 = A11^{-1}, S22 = A22^{-1}, S12 = -S11 A12 S22; A1 = I + S (A - U0)
+    = [[I + S12 A21, 0], [S22 A21, I]]; U1 = diag(I + S12 A21, I) is the
+    block upper part of A1 and L = I + U1^{-1} (A1 - U1) = [[I, 0],
+    [S22 A21, I]]. Then A = U0 U1 L. Returns (U0, U1, L, S)."""
+    A = _f64(A)
+    n = A.shape[0]
+    h = n // 2
+    A11, A12, A21, A22 = A[:h, :h], A[:h, h:], A[h:, :h], A[h:, h:]
+    S11 = inverse(A11)
+    S22 = inverse(A22)
+    S12 = -(S11 @ A12) @ S22
+    U0 = A.copy()
+    U0[h:, :h] = 0.0
+    S = np.zeros((n, n))
+    S[:h, :h], S[:h, h:], S[h:, h:] = S11, S12, S22
+    A1 = np.eye(n) + S @ (A - U0)
+    U1 = A1.copy()
+    U1[h:, :h] = 0.0
+    U1inv = np.eye(n)
+    U1inv[:h, :h] = inverse(A1[:h, :h])
+    Lb = np.eye(n) + U1inv @ (A1 - U1)
+    return U0, U1, Lb, S
+
+
+def brsi(A, base: int = 64) -> np.ndarray:
+    """A^{-1} by BRSI with gamma = 2 (Section 5, the gamma = 2 derivation):
+    with h = n // 2, S11 = A11^{-1}, S22 = A22^{-1} (both by this recursion),
+    S12 = -S11 A12 S22, W = (I + S12 A21)^{-1} (by this recursion),
+        A^{-1} = [[W S11, W S12], [-S22 A21 W S11, S22 - S22 A21 W S12]].
+    Orders <= base are inverted by ``inverse``. No pivoting: the diagonal
+    blocks met on the way must be invertible."""
+    A = _f64(A)
+    n = A.shape[0]
+    if n <= base:
+        return inverse(A)
+    h = n // 2
+    A11, A12, A21, A22 = A[:h, :h], A[:h, h:], A[h:, :h], A[h:, h:]
+    S11 = brsi(A11, base)
+    S22 = brsi(A22, base)
+    S12 = -(S11 @ A12) @ S22
+    W = brsi(np.eye(h) + S12 @ A21, base)
+    T = S22 @ A21
+    X = np.empty((n, n))
+    X[:h, :h] = W @ S11
+    X[:h, h:] = W @ S12
+    X[h:, :h] = -T @ X[:h, :h]
+    X[h:, h:] = S22 - T @ X[:h, h:]
+    return X
 
 
 def tril_inverse_backward(L, G) -> np.ndarray:

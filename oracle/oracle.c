@@ -357,6 +357,116 @@ ORACLE_API void oracle_residual_columns(int64_t n, const double *L, int64_t ldl,
   }
 }
 
+/*
+ * Algorithm SQR (Section 5): modified Gram-Schmidt QR of A (A = Q R, Q with
+ * orthonormal columns, R upper triangular with positive diagonal) with
+ * S = R^{-1} grown one column at a time beside R. For column j (0-based):
+ *   q^ = v_j;  for i < j: R(i, j) = q^ . q_i,  q^ -= R(i, j) q_i   (in order);
+ *   R(j, j) = ||q^||_2  (zero -> stop);  D(j, j) = 1 / R(j, j);  q_j = D(j, j) q^;
+ *   S'(j, j) = 1;  S'(i, j) = -(1 / R(j, j)) sum_{k=i}^{j-1} S'(i, k) R(k, j)  (i < j);
+ * and at the end S = D S' (row i of S' times D(i, i)). The column of S' uses
+ * R(j, j) of the same column, so it is formed once R(j, j) is known (S' is
+ * then the inverse of R D, whose diagonal is 1, and D S' = (R D D^{-1})^{-1}).
+ * Q, R, S are n x n row-major with leading dimension n; R and S are zero
+ * below the diagonal. Returns 0, or the 1-based index j + 1 of the first
+ * column with R(j, j) = 0 (the outputs are then incomplete).
+ */
+ORACLE_API int64_t oracle_sqr(int64_t n, const double *A, int64_t lda, double *Q, double *R, double *S) {
+  double *qh = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int64_t i = 0; i < n * n; ++i) {
+    Q[i] = 0.0;
+    R[i] = 0.0;
+    S[i] = 0.0;
+  }
+  int64_t bad = 0;
+  for (int64_t j = 0; j < n && !bad; ++j) {
+    for (int64_t r = 0; r < n; ++r) qh[r] = A[r * lda + j];
+    for (int64_t i = 0; i < j; ++i) {
+      double dot = 0.0;
+      for (int64_t r = 0; r < n; ++r) dot += qh[r] * Q[r * n + i];
+      R[i * n + j] = dot;
+      for (int64_t r = 0; r < n; ++r) qh[r] -= dot * Q[r * n + i];
+    }
+    double nrm = 0.0;
+    for (int64_t r = 0; r < n; ++r) nrm += qh[r] * qh[r];
+    nrm = sqrt(nrm);
+    R[j * n + j] = nrm;
+    if (nrm == 0.0) {
+      bad = j + 1;
+      break;
+    }
+    d[j] = 1.0 / nrm;
+    for (int64_t r = 0; r < n; ++r) Q[r * n + j] = d[j] * qh[r];
+    S[j * n + j] = 1.0;
+    for (int64_t i = 0; i < j; ++i) {
+      double s = 0.0;
+      for (int64_t k = i; k < j; ++k) s += S[i * n + k] * R[k * n + j];
+      S[i * n + j] = -s / nrm;
+    }
+  }
+  if (!bad)
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = i; j < n; ++j) S[i * n + j] *= d[i];
+  free(qh);
+  free(d);
+  return bad;
+}
+
+/*
+ * A^{-1} by its textbook construction: Gauss-Jordan elimination with partial
+ * pivoting on [A | I]. For column c: pick the row p >= c with the largest
+ * |a(p, c)|, swap rows p and c of both halves, divide row c by the pivot,
+ * then subtract a(r, c) times row c from every other row r. The right half is
+ * then A^{-1}. X is n x n row-major with leading dimension n. Returns 0, or
+ * c + 1 for the first column without a nonzero pivot (X is then incomplete).
+ */
+ORACLE_API int64_t oracle_inverse(int64_t n, const double *A, int64_t lda, double *X) {
+  size_t nn = (size_t)(n * n > 0 ? n * n : 1);
+  double *W = (double *)malloc(sizeof(double) * nn);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      W[i * n + j] = A[i * lda + j];
+      X[i * n + j] = (i == j) ? 1.0 : 0.0;
+    }
+  int64_t bad = 0;
+  for (int64_t c = 0; c < n; ++c) {
+    int64_t p = c;
+    for (int64_t r = c + 1; r < n; ++r)
+      if (fabs(W[r * n + c]) > fabs(W[p * n + c])) p = r;
+    if (W[p * n + c] == 0.0) {
+      bad = c + 1;
+      break;
+    }
+    if (p != c)
+      for (int64_t j = 0; j < n; ++j) {
+        double t = W[p * n + j];
+        W[p * n + j] = W[c * n + j];
+        W[c * n + j] = t;
+        t = X[p * n + j];
+        X[p * n + j] = X[c * n + j];
+        X[c * n + j] = t;
+      }
+    const double piv = W[c * n + c];
+    for (int64_t j = 0; j < n; ++j) {
+      W[c * n + j] /= piv;
+      X[c * n + j] /= piv;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = W[r * n + c];
+      if (f == 0.0) continue;
+      for (int64_t j = 0; j < n; ++j) {
+        W[r * n + j] -= f * W[c * n + j];
+        X[r * n + j] -= f * X[c * n + j];
+      }
+    }
+  }
+  free(W);
+  return bad;
+}
+
 /* Threads OpenMP will use (for the CPU-baseline report). */
 ORACLE_API int32_t oracle_num_threads(void) {
 #ifdef _OPENMP

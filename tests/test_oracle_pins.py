@@ -415,3 +415,141 @@ def test_crout_invariants_and_zero_pivot():
     with pytest.raises(oracle.SingularMatrix) as e:  # second pivot 1 - 1 * 1 = 0
         oracle.crout_lu(np.array([[1.0, 1.0, 0.0], [1.0, 1.0, 2.0], [0.0, 3.0, 1.0]]))
     assert e.value.index == 2
+
+
+# ---------------------------------------------------------------- SQR
+def test_sqr_printed_example(golden):
+    """Section 6: the SQR factors Q, R, S and Q^T of the printed 5x5 matrix,
+    to the four printed decimals (the printed A is itself rounded, so the
+    last printed digit may differ by one)."""
+    g = golden("sqr_5x5.txt")
+    np.testing.assert_allclose(g["QT"], g["Q"].T, atol=0)  # fixture sanity
+    Q, R, S, Ainv = oracle.sqr(g["A"])
+    np.testing.assert_allclose(Q, g["Q"], atol=2e-4)
+    np.testing.assert_allclose(R, g["R"], atol=2e-4)
+    np.testing.assert_allclose(S, g["S"], atol=2e-4)
+    np.testing.assert_allclose(Ainv, g["S"] @ g["QT"], atol=5e-4)
+    np.testing.assert_allclose(g["A"] @ Ainv, np.eye(5), atol=1e-12)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (7, 3), (60, 4), (200, 5)])
+def test_sqr_matches_householder_qr(n, seed):
+    """Against numpy's Householder QR (an independent algorithm) after the
+    sign normalisation R(j, j) > 0 that makes the QR factors unique."""
+    A = synth.normal(n, n, seed) / np.sqrt(n) + 2.0 * np.eye(n)
+    Q, R, S, Ainv = oracle.sqr(A)
+    Qh, Rh = np.linalg.qr(A)
+    sg = np.sign(np.diag(Rh))
+    Qh, Rh = Qh * sg, (Rh.T * sg).T
+    cond = np.linalg.cond(A)
+    tol = 1e-13 * cond * max(n, 1)
+    np.testing.assert_allclose(Q, Qh, atol=tol)
+    np.testing.assert_allclose(R, Rh, atol=tol * np.abs(Rh).max())
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.tril(S, -1) == 0)
+    assert np.all(np.diag(R) > 0)
+    I = np.eye(n)
+    assert np.abs(Q.T @ Q - I).max() < tol
+    assert np.abs(S @ R - I).max() < 1e-13 * cond
+    # S Q^T A - I = S (Q^T Q - I) R: the loss of orthogonality times cond(R)
+    assert np.abs(Ainv @ A - I).max() < 1e-13 * cond * cond
+    np.testing.assert_allclose(S, np.linalg.inv(Rh), atol=tol * np.abs(S).max())
+
+
+def test_sqr_upper_input_is_exact():
+    """For upper triangular A with a positive power-of-two diagonal,
+    Gram-Schmidt meets orthogonal columns e_1, e_2, ... and every norm and
+    reciprocal is exact: Q = I and R = A exactly, and S is the triangular
+    inverse of A (checked against the column recurrence applied to A^T)."""
+    n = 40
+    A = synth.upper_triangular(n, 9)
+    A[np.arange(n), np.arange(n)] = 2.0 ** (np.arange(n) % 5 - 2)
+    Q, R, S, _ = oracle.sqr(A)
+    assert np.array_equal(Q, np.eye(n))
+    assert np.array_equal(R, A)
+    np.testing.assert_allclose(S, oracle.tril_inverse(A.T).T, rtol=1e-13, atol=1e-15)
+
+
+def test_sqr_zero_column_reports_index():
+    A = synth.normal(6, 6, 7)
+    A[:, 3] = 0.0
+    with pytest.raises(oracle.SingularMatrix) as e:
+        oracle.sqr(A)
+    assert e.value.index == 4
+    B = synth.normal(6, 6, 8)
+    B[:, 4] = B[:, 1] * 2.0  # dependent column: its residual is (numerically) zero only by luck
+    Q, R, S, _ = oracle.sqr(B)
+    assert abs(R[4, 4]) < 1e-12 * np.abs(R).max()
+
+
+# ---------------------------------------------------------------- general inverse
+def test_inverse_closed_forms():
+    a, b, c, d = 3.0, -2.0, 5.0, 7.0
+    X = oracle.inverse(np.array([[a, b], [c, d]]))
+    det = a * d - b * c
+    np.testing.assert_allclose(X, np.array([[d, -b], [-c, a]]) / det, rtol=1e-15)
+    P = np.eye(9)[[3, 0, 8, 1, 7, 2, 6, 4, 5]]
+    assert np.array_equal(oracle.inverse(P), P.T)
+    D = np.diag(2.0 ** np.arange(-4, 5))
+    assert np.array_equal(oracle.inverse(D), np.diag(2.0 ** -np.arange(-4, 5)))
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (5, 2), (64, 3), (257, 4)])
+def test_inverse_matches_lapack(n, seed):
+    A = synth.normal(n, n, seed)
+    X = oracle.inverse(A)
+    cond = np.linalg.cond(A)
+    np.testing.assert_allclose(X, np.linalg.inv(A), atol=1e-14 * cond * np.abs(X).max())
+    assert np.abs(A @ X - np.eye(n)).max() < 1e-14 * cond * n
+
+
+def test_inverse_singular_reports_column():
+    A = synth.normal(5, 5, 3)
+    A[2] = A[0] + A[1]
+    A[:, 4] = 0.0
+    with pytest.raises(oracle.SingularMatrix) as e:
+        oracle.inverse(A)
+    assert e.value.index == 5
+
+
+# ---------------------------------------------------------------- BRSI (gamma = 2)
+@pytest.mark.parametrize("n,base", [(2, 1), (3, 1), (17, 4), (64, 8), (130, 16), (300, 64)])
+def test_brsi_matches_inverse(n, base):
+    A = synth.diag_dominant(n, 30 + n)
+    X = oracle.brsi(A, base)
+    np.testing.assert_allclose(X, oracle.inverse(A), atol=1e-13)
+    assert np.abs(A @ X - np.eye(n)).max() < 1e-13
+
+
+def test_brsi_2x2_closed_form():
+    a, b, c, d = 4.0, 1.0, -2.0, 3.0
+    X = oracle.brsi(np.array([[a, b], [c, d]]), base=1)
+    np.testing.assert_allclose(X, np.array([[d, -b], [-c, a]]) / (a * d - b * c), rtol=1e-15)
+
+
+def test_brsi_block_upper_input():
+    """A21 = 0: W = I and the inverse is the block triangular inverse
+    [[S11, -S11 A12 S22], [0, S22]] with an exactly zero lower block."""
+    n, h = 96, 48
+    A = synth.diag_dominant(n, 41)
+    A[h:, :h] = 0.0
+    X = oracle.brsi(A, base=16)
+    assert np.all(X[h:, :h] == 0.0)
+    S11 = oracle.inverse(A[:h, :h])
+    S22 = oracle.inverse(A[h:, h:])
+    np.testing.assert_allclose(X[:h, :h], S11, atol=1e-14)
+    np.testing.assert_allclose(X[h:, h:], S22, atol=1e-14)
+    np.testing.assert_allclose(X[:h, h:], -S11 @ A[:h, h:] @ S22, atol=1e-14)
+
+
+def test_brsi_split_factorization():
+    """Steps of BRSI with gamma = 2: A = U0 U1 L with U0 block upper, U1 block
+    diagonal, L unit block lower, and S = U0^{-1}."""
+    n, h = 80, 40
+    A = synth.diag_dominant(n, 43)
+    U0, U1, Lb, S = oracle.brsi_split(A)
+    assert np.all(U0[h:, :h] == 0) and np.all(U1[h:, :h] == 0) and np.all(U1[:h, h:] == 0)
+    assert np.all(Lb[:h, h:] == 0)
+    np.testing.assert_allclose(np.diag(Lb), 1.0, atol=1e-15)
+    np.testing.assert_allclose(U0 @ S, np.eye(n), atol=1e-14)
+    np.testing.assert_allclose(U0 @ U1 @ Lb, A, atol=1e-14)
+    np.testing.assert_allclose(oracle.inverse(Lb) @ oracle.inverse(U1) @ S, oracle.brsi(A, 8), atol=1e-13)
