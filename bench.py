@@ -232,6 +232,43 @@ def skul_secondary(P, torch, reps):
             "reps": reps}
 
 
+def sqr_secondary(P, torch, reps):
+    """Algorithm SQR at n = 4096, FP64: modified Gram-Schmidt A = Q R, S = R^-1
+    and Ainv = S Q^T; effective rate over 3 n^3 flops (2 n^3 for Gram-Schmidt,
+    n^3 / 3 for the triangular inverse, 2 n^3 / 3 for S Q^T)."""
+    import synth
+
+    n = 4096
+    A = torch.from_numpy(synth.diag_dominant(n, 22)).cuda()
+    P.sqr(A)
+    ms = time_events(torch, lambda: P.sqr(A, blocking=False), reps)
+    Q, R, S, Ainv = P.sqr(A)
+    eye = torch.eye(n, dtype=A.dtype, device=A.device)
+    orth = float(torch.linalg.norm(Q.T @ Q - eye) / n ** 0.5)
+    res = float(torch.linalg.norm(A @ Ainv - eye) / n ** 0.5)
+    return {"workload": f"SQR: Gram-Schmidt A = Q R with S = R^-1, Ainv = S Q^T; FP64 n={n}, diagonally dominant",
+            "ms": round(ms, 3), "tflops_3n3": round(3.0 * n ** 3 / ms / 1e9, 3), "orthogonality": orth,
+            "rel_inverse_residual": res, "reps": reps}
+
+
+def brsi_secondary(P, torch, reps):
+    """General inverse by BRSI (gamma = 2) at n = 4096, FP64; effective rate
+    over 2 n^3 flops (the Gauss-Jordan count of a general inverse; the
+    recursion itself executes about 3.2 n^3)."""
+    import synth
+
+    n = 4096
+    A = torch.from_numpy(synth.diag_dominant(n, 16)).cuda()
+    P.brsi(A)
+    ms = time_events(torch, lambda: P.brsi(A, blocking=False), reps)
+    X = P.brsi(A)
+    eye = torch.eye(n, dtype=A.dtype, device=A.device)
+    res = float(torch.linalg.norm(A @ X - eye) / n ** 0.5)
+    return {"workload": f"BRSI gamma=2: general inverse, FP64 n={n}, diagonally dominant",
+            "ms": round(ms, 3), "tflops_2n3": round(2.0 * n ** 3 / ms / 1e9, 3), "rel_inverse_residual": res,
+            "reps": reps}
+
+
 def cpu_baseline(L, seconds):
     """The oracle (column recurrence, all host cores via OpenMP) on a bounded
     sample of the same matrix: evenly spaced columns of L^-1."""
@@ -350,6 +387,12 @@ def main():
         log("SKUL n=4096 FP64")
         out["secondary"]["skul"] = skul_secondary(P, torch, 3)
         log(f"skul: {out['secondary']['skul']}")
+        log("SQR n=4096 FP64")
+        out["secondary"]["sqr"] = sqr_secondary(P, torch, 3)
+        log(f"sqr: {out['secondary']['sqr']}")
+        log("BRSI n=4096 FP64")
+        out["secondary"]["brsi"] = brsi_secondary(P, torch, 3)
+        log(f"brsi: {out['secondary']['brsi']}")
         if n == 16384:
             log("COMBRIT beta = 4, 8 (FP64)")
             out["secondary"]["combrit"] = combrit_secondary(P, torch, Ld, 3)

@@ -220,6 +220,47 @@ int trinv_skul(int mode, int64_t n, const void *A, void *L, void *U, void *S, vo
                const trinv_opts *opts, void *ws, size_t ws_bytes, trinv_stream_t stream, trinv_info *info);
 
 /*
+ * Algorithm SQR (Section 5): modified Gram-Schmidt A = Q R (Q with
+ * orthonormal columns, R upper triangular with positive diagonal) together
+ * with S = R^-1, so that S Q^T = A^-1; optionally Ainv = S Q^T.
+ * mode: TRINV_F64 or TRINV_F32; n <= 4096 (else TRINV_ERR_UNSUPPORTED).
+ * A: device n x n row-major (leading dimension n), read only; Q, R, S (and
+ * Ainv if not NULL): device n x n outputs written in full (R and S zero below
+ * the diagonal), none overlapping A or each other (else TRINV_ERR_ARG).
+ * opts: leaf (the triangular inverse), blocking; upper / unit_diag / beta > 2
+ * give TRINV_ERR_UNSUPPORTED. ws: trinv_sqr_workspace_bytes bytes (holds a
+ * working copy of A). A column whose orthogonalized part is exactly zero
+ * (rank deficiency) makes the outputs non-finite and, with blocking, returns
+ * TRINV_ERR_SINGULAR with info->first_bad_index = that column (1-based).
+ * info: nullable.
+ */
+size_t trinv_sqr_workspace_bytes(int mode, int64_t n, const trinv_opts *opts);
+int trinv_sqr(int mode, int64_t n, const void *A, void *Q, void *R, void *S, void *Ainv,
+              const trinv_opts *opts, void *ws, size_t ws_bytes, trinv_stream_t stream, trinv_info *info);
+
+/*
+ * General inverse by BRSI with gamma = 2 (Section 5, Steps of BRSI and the
+ * gamma = 2 derivation): with S11 = A11^-1, S22 = A22^-1, S12 = -S11 A12 S22
+ * and W = (I + S12 A21)^-1, all inverses by the same recursion,
+ *   A^-1 = [[W S11, W S12], [-S22 A21 W S11, S22 - S22 A21 W S12]].
+ * No pivoting: every diagonal block met by the recursion must be invertible
+ * (e.g. A symmetric positive definite or diagonally dominant). The order is
+ * padded internally to b 2^k (b <= 128) with an identity tail.
+ * mode: TRINV_F64 or TRINV_F32. A: device n x n, leading dimension lda >= n,
+ * read only; Ainv: device n x n, leading dimension ldx >= n, not overlapping
+ * A (else TRINV_ERR_ARG). opts: blocking; upper / unit_diag / beta > 2 give
+ * TRINV_ERR_UNSUPPORTED. ws: trinv_brsi_workspace_bytes bytes (about 4 n^2
+ * elements). A zero pivot in a bottom-level block makes the output
+ * non-finite and, with blocking, returns TRINV_ERR_SINGULAR with
+ * info->first_bad_index = the 1-based position of that pivot inside its
+ * bottom-level block (the blocks are copies, so no global index exists).
+ * info: nullable.
+ */
+size_t trinv_brsi_workspace_bytes(int mode, int64_t n, const trinv_opts *opts);
+int trinv_brsi(int mode, int64_t n, const void *A, int64_t lda, void *Ainv, int64_t ldx,
+               const trinv_opts *opts, void *ws, size_t ws_bytes, trinv_stream_t stream, trinv_info *info);
+
+/*
  * Measurement helper (not part of the method): FP64 relative residual of a
  * candidate inverse, computed on the GPU with FP64 MFMA products:
  *   out_host[0] = ||L X - I||_F, [1] = ||tril(L)||_F, [2] = ||X||_F.

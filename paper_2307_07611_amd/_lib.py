@@ -22,7 +22,8 @@ EXPORTS = [
     "trinv_batched_workspace_bytes", "trinv_tril_inverse_batched", "trinv_backward_workspace_bytes",
     "trinv_tril_inverse_backward", "trinv_factored_workspace_bytes", "trinv_factored_inverse",
     "trinv_residual_workspace_bytes", "trinv_residual", "trinv_profile_enable", "trinv_profile_read",
-    "trinv_skul_workspace_bytes", "trinv_skul",
+    "trinv_skul_workspace_bytes", "trinv_skul", "trinv_sqr_workspace_bytes", "trinv_sqr",
+    "trinv_brsi_workspace_bytes", "trinv_brsi",
 ]
 
 
@@ -86,6 +87,16 @@ def load():
     lib.trinv_skul.argtypes = [ctypes.c_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Opts), _vp, _sz,
                                _vp, ctypes.POINTER(Info)]
     lib.trinv_skul.restype = ctypes.c_int
+    lib.trinv_sqr_workspace_bytes.argtypes = [ctypes.c_int, _i64, ctypes.POINTER(Opts)]
+    lib.trinv_sqr_workspace_bytes.restype = _sz
+    lib.trinv_sqr.argtypes = [ctypes.c_int, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(Opts), _vp, _sz, _vp,
+                              ctypes.POINTER(Info)]
+    lib.trinv_sqr.restype = ctypes.c_int
+    lib.trinv_brsi_workspace_bytes.argtypes = [ctypes.c_int, _i64, ctypes.POINTER(Opts)]
+    lib.trinv_brsi_workspace_bytes.restype = _sz
+    lib.trinv_brsi.argtypes = [ctypes.c_int, _i64, _vp, _i64, _vp, _i64, ctypes.POINTER(Opts), _vp, _sz, _vp,
+                               ctypes.POINTER(Info)]
+    lib.trinv_brsi.restype = ctypes.c_int
     lib.trinv_residual_workspace_bytes.argtypes = [ctypes.c_int, _i64]
     lib.trinv_residual_workspace_bytes.restype = _sz
     lib.trinv_residual.argtypes = [ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp,

@@ -198,6 +198,46 @@ def skul(A: torch.Tensor, *, want_ainv=True, leaf=0, blocking=True):
     return L, U, S, K, Ainv
 
 
+def sqr(A: torch.Tensor, *, want_ainv=True, leaf=0, blocking=True):
+    """Algorithm SQR: (Q, R, S, Ainv) with A = Q R (modified Gram-Schmidt,
+    R(j, j) > 0), S = R^-1 and Ainv = S Q^T (None if not wanted)."""
+    _check_dev(A)
+    A = A.contiguous()
+    m = _mode_for(A, None)
+    n = A.shape[0]
+    Q, R, S = (torch.empty_like(A) for _ in range(3))
+    Ainv = torch.empty_like(A) if want_ainv else None
+    lib = _lib.load()
+    o = _opts(leaf=leaf, blocking=blocking)
+    ws = _workspace(lib.trinv_sqr_workspace_bytes(m, n, ctypes.byref(o)), A.device)
+    info = _lib.Info()
+    st = lib.trinv_sqr(m, n, A.data_ptr(), Q.data_ptr(), R.data_ptr(), S.data_ptr(),
+                       Ainv.data_ptr() if want_ainv else None, ctypes.byref(o), ws.data_ptr(), ws.numel(), _stream(),
+                       ctypes.byref(info))
+    if st != _lib.OK:
+        raise _lib.TrinvError(st, "trinv_sqr", _info_dict(info))
+    return Q, R, S, Ainv
+
+
+def brsi(A: torch.Tensor, *, blocking=True):
+    """General inverse by BRSI with gamma = 2 (no pivoting)."""
+    _check_dev(A)
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1:
+        raise ValueError("brsi: A must be a square matrix with unit column stride")
+    m = _mode_for(A, None)
+    n = A.shape[0]
+    X = torch.empty((n, n), dtype=A.dtype, device=A.device)
+    lib = _lib.load()
+    o = _opts(blocking=blocking)
+    ws = _workspace(lib.trinv_brsi_workspace_bytes(m, n, ctypes.byref(o)), A.device)
+    info = _lib.Info()
+    st = lib.trinv_brsi(m, n, A.data_ptr(), max(A.stride(0), 1), X.data_ptr(), n, ctypes.byref(o), ws.data_ptr(),
+                        ws.numel(), _stream(), ctypes.byref(info))
+    if st != _lib.OK:
+        raise _lib.TrinvError(st, "trinv_brsi", _info_dict(info))
+    return X
+
+
 class BatchedGraph:
     """A fixed batch layout with static device buffers whose inversion is
     captured once in a graph (``torch.cuda.CUDAGraph``) and replayed.

@@ -1,6 +1,8 @@
 // Internal definitions shared by the HIP sources of libtrinv (gfx950 only).
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -37,5 +39,16 @@ __device__ __forceinline__ int64_t imax64(int64_t a, int64_t b) { return a > b ?
 // Round-to-nearest-even conversions (the hardware conversion instructions).
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 __device__ __forceinline__ _Float16 to_f16(float x) { return (_Float16)x; }
+
+// Calls f(integral_constant<int, B>), ..., f(integral_constant<int, E-1>): the
+// index is a compile-time constant in every call, so register arrays indexed
+// by it never need memory.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 }  // namespace trinv

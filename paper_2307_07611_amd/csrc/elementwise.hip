@@ -178,6 +178,35 @@ template hipError_t launch_block_copy<double>(const double*, int64_t, int64_t, d
 template hipError_t launch_block_copy<float>(const float*, int64_t, int64_t, float*, int64_t, int64_t, int64_t,
                                              int64_t, float, hipStream_t);
 
+// dst block b (m x m) = [[src block b (n x n), 0], [0, I]] (n <= m; src null:
+// the identity), blocks at strides sstride / dstride.
+template <typename T>
+__global__ void k_embed(const T* src, int64_t lds, int64_t sstride, int64_t n, T* dst, int64_t ldd, int64_t dstride,
+                        int64_t m, int64_t nblocks) {
+  const int64_t total = nblocks * m * m;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / (m * m), r = (e / m) % m, c = e % m;
+    T v = (r == c) ? T(1) : T(0);
+    if (src && r < n && c < n) v = src[b * sstride + r * lds + c];
+    dst[b * dstride + r * ldd + c] = v;
+  }
+}
+
+template <typename T>
+hipError_t launch_embed(const T* src, int64_t lds, int64_t sstride, int64_t n, T* dst, int64_t ldd, int64_t dstride,
+                        int64_t m, int64_t nblocks, hipStream_t s) {
+  if (m <= 0 || nblocks <= 0) return hipSuccess;
+  if (n > m) return hipErrorInvalidValue;
+  const int64_t total = nblocks * m * m, blocks = (total + 255) / 256;
+  hipLaunchKernelGGL((k_embed<T>), dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, src, lds,
+                     sstride, n, dst, ldd, dstride, m, nblocks);
+  return hipGetLastError();
+}
+template hipError_t launch_embed<double>(const double*, int64_t, int64_t, int64_t, double*, int64_t, int64_t, int64_t,
+                                         int64_t, hipStream_t);
+template hipError_t launch_embed<float>(const float*, int64_t, int64_t, int64_t, float*, int64_t, int64_t, int64_t,
+                                        int64_t, hipStream_t);
+
 __global__ void k_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     status[i] = first_bad[i] == ~0ull ? 0 : (int32_t)first_bad[i];

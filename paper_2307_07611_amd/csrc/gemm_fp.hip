@@ -437,6 +437,18 @@ hipError_t launch_gemm(const GemmArgs<TI>& a, hipStream_t s) {
   if (!a.a_trans && !a.b_trans && a.amask == 0 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kColAsc &&
       a.klo == kLoZero && a.khi == kHiK && ep == (kEpStore | kEpAccum))
     return go<TI, TC, 0, 0, 0, 0, kAllTiles, kColAsc, kLoZero, kHiK, kEpStore | kEpAccum>(a, s, total);
+  // plain product, full K: the block products of BRSI
+  if (!a.a_trans && !a.b_trans && a.amask == 0 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kColAsc &&
+      a.klo == kLoZero && a.khi == kHiK && ep == kEpStore)
+    return go<TI, TC, 0, 0, 0, 0, kAllTiles, kColAsc, kLoZero, kHiK, kEpStore>(a, s, total);
+  // projections of block Gram-Schmidt (SQR): Q_k^T V, A read transposed
+  if (a.a_trans && !a.b_trans && a.amask == 0 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kColAsc &&
+      a.klo == kLoZero && a.khi == kHiK && ep == kEpStore)
+    return go<TI, TC, 1, 0, 0, 0, kAllTiles, kColAsc, kLoZero, kHiK, kEpStore>(a, s, total);
+  // SQR inverse S Q^T: A upper (k >= row), B read transposed
+  if (!a.a_trans && a.b_trans && a.amask == 0 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kColAsc &&
+      a.klo == kLoM0 && a.khi == kHiK && ep == kEpStore)
+    return go<TI, TC, 0, 1, 0, 0, kAllTiles, kColAsc, kLoM0, kHiK, kEpStore>(a, s, total);
   // residual check: tril(L) * X - I, norm only
   if (!a.a_trans && !a.b_trans && a.amask == 1 && a.bmask == 0 && a.tiles == kAllTiles && a.order == kRowDesc &&
       a.klo == kLoZero && a.khi == kHiM1 && ep == (kEpSubI | kEpTileSq))

@@ -27,17 +27,6 @@
 
 namespace trinv {
 
-// Calls f(integral_constant<int, B>), ..., f(integral_constant<int, E-1>): the
-// index is a compile-time constant in every call, so register arrays indexed
-// by it never need memory.
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
-}
-
 namespace {
 constexpr int LT = 256;  // workgroup tile (rows and columns)
 

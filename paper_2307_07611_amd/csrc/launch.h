@@ -117,9 +117,12 @@ hipError_t launch_maxabs(const T* A, int64_t n, int64_t lda, int lower, int unit
 // W[0:nb, 0:nb] (nb <= 128) into the L block (lower) and the U block (unit
 // upper) at L / U (leading dimension ld) and writes their inverses K = L^-1,
 // S = U^-1 at K / S (leading dimension ldk); zero pivots -> *bad (row0 + p + 1).
+// A batch of `count` blocks at strides sw (W), slu (L, U) and sk (K, S) runs
+// in one launch, one workgroup per block.
 template <typename T>
-hipError_t launch_crout_diag(const T* W, int64_t ldw, int nb, T* L, T* U, int64_t ld, T* K, T* S, int64_t ldk,
-                             int64_t row0, uint64_t* bad, hipStream_t s);
+hipError_t launch_crout_diag(const T* W, int64_t ldw, int64_t sw, int nb, T* L, T* U, int64_t ld, int64_t slu, T* K,
+                             T* S, int64_t ldk, int64_t sk, int64_t count, int64_t row0, uint64_t* bad,
+                             hipStream_t s);
 // Zero bytes [p, p + bytes) (a multiple of 4) with a kernel (no memset node).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // out[0] = min over blocks b of (b * m + words[b]) over the set words (all ones = unset).
@@ -129,6 +132,20 @@ hipError_t launch_fold_status(const uint64_t* words, int64_t count, int64_t m, u
 template <typename T>
 hipError_t launch_block_copy(const T* src, int64_t lds, int64_t sstride, T* dst, int64_t ldd, int64_t dstride,
                              int64_t m, int64_t nblocks, T alpha, hipStream_t s);
+// Panel step of blocked modified Gram-Schmidt (sqr.hip): orthogonalizes the
+// columns p0 .. p0 + w - 1 of V (n x n, leading dimension ld, n <= 4096,
+// w <= mgs_panel_width(n)) among themselves in one workgroup, writing those
+// columns of Q and the block R[p0 : p0 + w, p0 : p0 + w]; a zero norm sends
+// p0 + j + 1 to *bad.
+int mgs_panel_width(int64_t n);
+template <typename T>
+hipError_t launch_mgs_panel(const T* V, T* Q, T* R, int64_t ld, int64_t n, int64_t p0, int w, uint64_t* bad,
+                            hipStream_t s);
+// dst block b (m x m) = [[src block b (n x n), 0], [0, I]] for n <= m (src
+// null: the identity), blocks at strides sstride / dstride.
+template <typename T>
+hipError_t launch_embed(const T* src, int64_t lds, int64_t sstride, int64_t n, T* dst, int64_t ldd, int64_t dstride,
+                        int64_t m, int64_t nblocks, hipStream_t s);
 // status[i] = first_bad[i] == all ones ? 0 : first_bad[i]  (int32 per matrix).
 hipError_t launch_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count, hipStream_t s);
 // B = A^T for an n x n matrix.

@@ -55,8 +55,8 @@ hipError_t skul_lu(int64_t n, const T* A, T* L, T* U, const WsSkul& w, hipStream
     {
       snprintf(cls, sizeof(cls), "%s_skul_diag", pre);
       ProfLaunch pl(cls, 4.0 * b * b * b / 3.0, sizeof(T) * 5.0 * b * b, s);
-      if ((e = launch_crout_diag<T>(W + k0 * n + k0, n, (int)b, L + k0 * n + k0, U + k0 * n + k0, n, Kb, Sb, kNb, k0,
-                                    w.status, s)) != hipSuccess)
+      if ((e = launch_crout_diag<T>(W + k0 * n + k0, n, 0, (int)b, L + k0 * n + k0, U + k0 * n + k0, n, 0, Kb, Sb, kNb,
+                                    0, 1, k0, w.status, s)) != hipSuccess)
         return e;
     }
     if (rest == 0) break;

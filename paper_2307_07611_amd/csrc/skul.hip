@@ -92,17 +92,24 @@ __device__ __forceinline__ void crout_phase(T (&v)[8][8], int nb, int tx, int ty
 }
 }  // namespace
 
-// One workgroup of 256 threads factors the block W[0:nb, 0:nb] (nb <= 128,
-// leading dimension ldw) and writes: L (lower, diagonal included) and U (unit
+// One workgroup of 256 threads per block (blockIdx.x selects the block of a
+// strided batch) factors the block W[0:nb, 0:nb] (nb <= 128, leading
+// dimension ldw) and writes: L (lower, diagonal included) and U (unit
 // upper) of the block, zeros elsewhere, at leading dimension ld; K = L^-1
 // (lower, zeros above) and S = U^-1 (unit upper, zeros below) at leading
 // dimension ldk. The 1-based index row0 + p + 1 of the first zero pivot goes to
 // *bad (atomic minimum); the factors are then not finite.
 template <typename T>
-__global__ __launch_bounds__(256) void k_crout_diag(const T* __restrict__ W, int64_t ldw, int nb, T* __restrict__ L,
-                                                    T* __restrict__ U, int64_t ld, T* __restrict__ K,
-                                                    T* __restrict__ S, int64_t ldk, int64_t row0, uint64_t* bad) {
+__global__ __launch_bounds__(256) void k_crout_diag(const T* __restrict__ W, int64_t ldw, int64_t sw, int nb,
+                                                    T* __restrict__ L, T* __restrict__ U, int64_t ld, int64_t slu,
+                                                    T* __restrict__ K, T* __restrict__ S, int64_t ldk, int64_t sk,
+                                                    int64_t row0, uint64_t* bad) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
+  W += blockIdx.x * sw;
+  L += blockIdx.x * slu;
+  U += blockIdx.x * slu;
+  K += blockIdx.x * sk;
+  S += blockIdx.x * sk;
   T* LU = (T*)smem;
   T* buf = LU + kMaxNb * kLuStride;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -145,9 +152,11 @@ __global__ __launch_bounds__(256) void k_crout_diag(const T* __restrict__ W, int
 }
 
 template <typename T>
-hipError_t launch_crout_diag(const T* W, int64_t ldw, int nb, T* L, T* U, int64_t ld, T* K, T* S, int64_t ldk,
-                             int64_t row0, uint64_t* bad, hipStream_t s) {
-  if (nb <= 0) return hipSuccess;
+hipError_t launch_crout_diag(const T* W, int64_t ldw, int64_t sw, int nb, T* L, T* U, int64_t ld, int64_t slu, T* K,
+                             T* S, int64_t ldk, int64_t sk, int64_t count, int64_t row0, uint64_t* bad,
+                             hipStream_t s) {
+  if (nb <= 0 || count <= 0) return hipSuccess;
+  if (count > 0x7fffffff) return hipErrorInvalidValue;
   if (nb > kMaxNb || ldk < nb) return hipErrorInvalidValue;
   const size_t lds = sizeof(T) * ((size_t)kMaxNb * kLuStride + 4 * kMaxNb);
   static bool attr_set = false;  // per instantiation
@@ -157,13 +166,16 @@ hipError_t launch_crout_diag(const T* W, int64_t ldw, int nb, T* L, T* U, int64_
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_crout_diag<T>, dim3(1), dim3(256), lds, s, W, ldw, nb, L, U, ld, K, S, ldk, row0, bad);
+  hipLaunchKernelGGL(k_crout_diag<T>, dim3((unsigned)count), dim3(256), lds, s, W, ldw, sw, nb, L, U, ld, slu, K, S,
+                     ldk, sk, row0, bad);
   return hipGetLastError();
 }
 
-template hipError_t launch_crout_diag<double>(const double*, int64_t, int, double*, double*, int64_t, double*, double*,
-                                              int64_t, int64_t, uint64_t*, hipStream_t);
-template hipError_t launch_crout_diag<float>(const float*, int64_t, int, float*, float*, int64_t, float*, float*,
-                                             int64_t, int64_t, uint64_t*, hipStream_t);
+template hipError_t launch_crout_diag<double>(const double*, int64_t, int64_t, int, double*, double*, int64_t, int64_t,
+                                              double*, double*, int64_t, int64_t, int64_t, int64_t, uint64_t*,
+                                              hipStream_t);
+template hipError_t launch_crout_diag<float>(const float*, int64_t, int64_t, int, float*, float*, int64_t, int64_t,
+                                             float*, float*, int64_t, int64_t, int64_t, int64_t, uint64_t*,
+                                             hipStream_t);
 
 }  // namespace trinv

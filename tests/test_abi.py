@@ -165,3 +165,48 @@ def test_combrit_argument_errors_before_any_launch(lib):
     o.beta = 4
     w4 = lib.trinv_workspace_bytes(_lib.F64, 1024, ctypes.byref(o))
     assert w4 >= 2 * 1024 * 1024 * 8 > w2  # B and its inverse, n x n each
+
+
+def test_sqr_brsi_argument_errors_before_any_launch(lib):
+    from paper_2307_07611_amd import _lib
+
+    o = _lib.Opts()
+    lib.trinv_default_opts(ctypes.byref(o))
+    A, Q, R, S, X = 1 << 30, 1 << 34, 1 << 35, 1 << 36, 1 << 37
+
+    def sqr(mode, n, **kw):
+        oo = _lib.Opts()
+        lib.trinv_default_opts(ctypes.byref(oo))
+        for k, v in kw.items():
+            setattr(oo, k, v)
+        return lib.trinv_sqr(mode, n, A, Q, R, S, X, ctypes.byref(oo), None, 0, None, None)
+
+    assert sqr(_lib.F64, -1) == _lib.ERR_ARG
+    assert sqr(_lib.F64, 0) == _lib.OK
+    assert lib.trinv_sqr(_lib.F64, 10, A, None, R, S, X, ctypes.byref(o), None, 0, None, None) == _lib.ERR_ARG
+    assert lib.trinv_sqr(_lib.F64, 10, A, A + 8, R, S, X, ctypes.byref(o), None, 0, None, None) == _lib.ERR_ARG
+    assert sqr(_lib.BF16_REFINE, 10) == _lib.ERR_UNSUPPORTED
+    assert sqr(_lib.F64, 4097) == _lib.ERR_UNSUPPORTED
+    assert sqr(_lib.F64, 100, upper=1) == _lib.ERR_UNSUPPORTED
+    assert sqr(_lib.F64, 100) == _lib.ERR_WORKSPACE
+    assert lib.trinv_sqr_workspace_bytes(_lib.F64, 1000, None) >= 1000 * 1000 * 8
+
+    def brsi(mode, n, lda, ldx, **kw):
+        oo = _lib.Opts()
+        lib.trinv_default_opts(ctypes.byref(oo))
+        for k, v in kw.items():
+            setattr(oo, k, v)
+        return lib.trinv_brsi(mode, n, A, lda, X, ldx, ctypes.byref(oo), None, 0, None, None)
+
+    assert brsi(_lib.F64, -1, 1, 1) == _lib.ERR_ARG
+    assert brsi(_lib.F64, 0, 0, 0) == _lib.OK
+    assert brsi(_lib.F64, 100, 99, 100) == _lib.ERR_ARG
+    assert brsi(_lib.F64, 100, 100, 99) == _lib.ERR_ARG
+    assert lib.trinv_brsi(_lib.F64, 100, A, 100, A + 800, 100, ctypes.byref(o), None, 0, None, None) == _lib.ERR_ARG
+    assert brsi(_lib.F16_REFINE, 100, 100, 100) == _lib.ERR_UNSUPPORTED
+    assert brsi(_lib.F64, 100, 100, 100, unit_diag=1) == _lib.ERR_UNSUPPORTED
+    assert brsi(_lib.F64, 100, 100, 100) == _lib.ERR_WORKSPACE
+    # about 4 n^2 elements for n = b 2^k; padded orders round up
+    w = lib.trinv_brsi_workspace_bytes(_lib.F64, 1024, None)
+    assert 3 * 1024 * 1024 * 8 <= w <= 5 * 1024 * 1024 * 8
+    assert lib.trinv_brsi_workspace_bytes(_lib.F64, 129, None) >= 2 * 130 * 130 * 8
