@@ -207,6 +207,34 @@ template hipError_t launch_embed<double>(const double*, int64_t, int64_t, int64_
 template hipError_t launch_embed<float>(const float*, int64_t, int64_t, int64_t, float*, int64_t, int64_t, int64_t,
                                         int64_t, hipStream_t);
 
+// dst (rows x cols, leading dimension ldd) = sum over c < count of the
+// matrices src + c stride (leading dimension lds), summed in order of c.
+template <typename T>
+__global__ void k_sum_blocks(const T* __restrict__ src, int64_t lds, int64_t stride, int64_t count, int64_t rows,
+                             int64_t cols, T* __restrict__ dst, int64_t ldd) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / cols, c = e % cols;
+    T v = T(0);
+    for (int64_t b = 0; b < count; ++b) v += src[b * stride + r * lds + c];
+    dst[r * ldd + c] = v;
+  }
+}
+
+template <typename T>
+hipError_t launch_sum_blocks(const T* src, int64_t lds, int64_t stride, int64_t count, int64_t rows, int64_t cols,
+                             T* dst, int64_t ldd, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int64_t total = rows * cols, blocks = (total + 255) / 256;
+  hipLaunchKernelGGL((k_sum_blocks<T>), dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, src, lds,
+                     stride, count, rows, cols, dst, ldd);
+  return hipGetLastError();
+}
+template hipError_t launch_sum_blocks<double>(const double*, int64_t, int64_t, int64_t, int64_t, int64_t, double*,
+                                              int64_t, hipStream_t);
+template hipError_t launch_sum_blocks<float>(const float*, int64_t, int64_t, int64_t, int64_t, int64_t, float*,
+                                             int64_t, hipStream_t);
+
 __global__ void k_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     status[i] = first_bad[i] == ~0ull ? 0 : (int32_t)first_bad[i];

@@ -146,6 +146,10 @@ hipError_t launch_mgs_panel(const T* V, T* Q, T* R, int64_t ld, int64_t n, int64
 template <typename T>
 hipError_t launch_embed(const T* src, int64_t lds, int64_t sstride, int64_t n, T* dst, int64_t ldd, int64_t dstride,
                         int64_t m, int64_t nblocks, hipStream_t s);
+// dst (rows x cols) = sum over c < count of src + c stride, in order of c.
+template <typename T>
+hipError_t launch_sum_blocks(const T* src, int64_t lds, int64_t stride, int64_t count, int64_t rows, int64_t cols,
+                             T* dst, int64_t ldd, hipStream_t s);
 // status[i] = first_bad[i] == all ones ? 0 : first_bad[i]  (int32 per matrix).
 hipError_t launch_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count, hipStream_t s);
 // B = A^T for an n x n matrix.

@@ -6,7 +6,8 @@
 //   1. a panel is orthogonalized column by column in one workgroup (its
 //      columns of Q and its diagonal block of R);
 //   2. the later columns of the outer block lose the panel's components:
-//      R_pJ = Q_p^T V_J, V_J -= Q_p R_pJ (FP64 / FP32 MFMA products);
+//      R_pJ = Q_p^T V_J (split over row chunks, partial products summed in a
+//      fixed order), V_J -= Q_p R_pJ (FP64 / FP32 MFMA products);
 //   3. once the outer block is done, the same two products with its 128
 //      columns update every later column.
 // Inside a panel the projections are applied one column at a time, as
@@ -27,6 +28,9 @@ namespace {
 
 constexpr int64_t kOuter = 128;
 constexpr int64_t kMaxN = 4096;  // the panel holds a column in one workgroup's registers
+constexpr int64_t kChunk = 256;  // rows per partial product of a projection (split K)
+
+int64_t chunks(int64_t n) { return (n + kChunk - 1) / kChunk; }
 
 trinv_opts upper_opts(const trinv_opts& o) {
   trinv_opts u = o;
@@ -40,7 +44,7 @@ trinv_opts upper_opts(const trinv_opts& o) {
 
 struct WsSqr {
   uint64_t* status;
-  void *V, *tws;
+  void *V, *part, *tws;
   size_t tws_bytes;
 };
 
@@ -49,6 +53,7 @@ WsSqr carve_sqr(Carve& c, int mode, int64_t n, const trinv_opts& o) {
   const size_t es = mode == TRINV_F32 ? 4 : 8;
   w.status = c.take<uint64_t>(1);
   w.V = c.take<char>(es * (size_t)n * n);
+  w.part = c.take<char>(es * (size_t)chunks(n) * kOuter * n);
   const trinv_opts u = upper_opts(o);
   w.tws_bytes = trinv_workspace_bytes(mode, n, &u);
   w.tws = c.take<char>(w.tws_bytes);
@@ -57,28 +62,33 @@ WsSqr carve_sqr(Carve& c, int mode, int64_t n, const trinv_opts& o) {
 
 // R[r0 : r0 + m, c0 : c0 + nc] = Q[:, r0 : r0 + m]^T V[:, c0 : c0 + nc], then
 // V[:, c0 : c0 + nc] -= Q[:, r0 : r0 + m] R[r0 : r0 + m, c0 : c0 + nc].
+// The first product has a short output and a long K (the n rows): it runs
+// as one launch of partial products over row chunks of kChunk (the merges of
+// the launch), summed in chunk order by a second kernel.
 template <typename T>
-hipError_t project(int64_t n, const T* Q, T* R, T* V, int64_t r0, int64_t m, int64_t c0, int64_t nc,
+hipError_t project(int64_t n, const T* Q, T* R, T* V, int64_t r0, int64_t m, int64_t c0, int64_t nc, T* part,
                    const char* pre, hipStream_t s) {
   char cls[32];
   const double fm = (double)m, fn = (double)n, fc = (double)nc;
+  const int64_t nch = chunks(n);
   hipError_t e;
   {
     GemmArgs<T> g{};
-    g.A = {Q + r0, n, 0, 0};  // read transposed: A(i, k) = Q[k n + r0 + i]
+    g.A = {Q + r0, n, kChunk * n, 0};  // read transposed: A(i, k) = Q[(k + z kChunk) n + r0 + i]
     g.a_trans = 1;
-    g.B = {V + c0, n, 0, 0};
-    g.D = {R + r0 * n + c0, n, 0, 0};
+    g.B = {V + c0, n, kChunk * n, 0};
+    g.D = {part, nc, m * nc, 0};
     g.alpha = 1.0;
     g.tiles = kAllTiles;
     g.order = kColAsc;
     g.klo = kLoZero;
     g.khi = kHiK;
-    g.bt = {1, 1, m, nc, n, m, nc, n};
+    g.bt = {nch, 1, m, nc, kChunk, m, nc, n - (nch - 1) * kChunk};
     snprintf(cls, sizeof(cls), "%s_sqr_proj", pre);
-    ProfLaunch pl(cls, 2.0 * fm * fc * fn, sizeof(T) * (fm * fn + fn * fc + fm * fc), s);
+    ProfLaunch pl(cls, 2.0 * fm * fc * fn, sizeof(T) * (fm * fn + fn * fc + nch * fm * fc), s);
     if ((e = launch_gemm<T, T>(g, s)) != hipSuccess) return e;
   }
+  if ((e = launch_sum_blocks<T>(part, nc, m * nc, nch, m, nc, R + r0 * n + c0, n, s)) != hipSuccess) return e;
   GemmArgs<T> g{};
   g.A = {Q + r0, n, 0, 0};
   g.B = {R + r0 * n + c0, n, 0, 0};
@@ -113,9 +123,11 @@ hipError_t sqr_qr(int64_t n, const T* A, T* Q, T* R, const WsSqr& w, hipStream_t
         ProfLaunch pl(cls, 2.0 * n * wd * wd, sizeof(T) * 2.0 * n * wd, s);
         if ((e = launch_mgs_panel<T>(V, Q, R, n, n, p0, (int)wd, w.status, s)) != hipSuccess) return e;
       }
-      if (p1 < ob1 && (e = project<T>(n, Q, R, V, p0, wd, p1, ob1 - p1, pre, s)) != hipSuccess) return e;
+      if (p1 < ob1 && (e = project<T>(n, Q, R, V, p0, wd, p1, ob1 - p1, (T*)w.part, pre, s)) != hipSuccess)
+        return e;
     }
-    if (ob1 < n && (e = project<T>(n, Q, R, V, ob0, ob1 - ob0, ob1, n - ob1, pre, s)) != hipSuccess) return e;
+    if (ob1 < n && (e = project<T>(n, Q, R, V, ob0, ob1 - ob0, ob1, n - ob1, (T*)w.part, pre, s)) != hipSuccess)
+      return e;
   }
   return hipSuccess;
 }
