@@ -446,11 +446,70 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
         }
       }
       if constexpr (EPI == kLpEpResid || EPI == kLpEpCorr) {
-        // Gather the block's FP64 / FP32 operands first, all loads
+        const int64_t rbase = m0 + wm * 128 + i * 32 + 4 * (lane >> 5);
+        if (full) {
+          // Interior tile: every (row, col) of the block lies inside the
+          // matrix, so every load and store is unconditional and elements
+          // above the diagonal (diagonal tiles only) are selected to zero.
+          // Branches around single stores would make each store wait for
+          // all earlier memory operations, earlier stores included.
+          double xv[16], dv[16], ov[16];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int k = 4 * q + e;
+              const int64_t row = rbase + 8 * q + e;
+              if constexpr (EPI == kLpEpResid) {
+                xv[k] = Xr[row * a.ldx + col];
+                ov[k] = Lr[row * a.ldl + col];
+                dv[k] = dLr[row];
+              } else {
+                xv[k] = a.X[row * a.ldx + col];
+                ov[k] = (double)R32r[row * a.ldr + col];
+                dv[k] = dXr[row];
+              }
+            }
+          if constexpr (EPI == kLpEpResid) {
+            const double xjj = dXr[col];
+            double rv[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+              const int64_t row = rbase + 8 * (k >> 2) + (k & 3);
+              const bool ok = col <= row;
+              const double v = (row == col) ? fma(-dv[k], xv[k], 1.0)
+                                            : -(alpha * (double)blk[k]) - dv[k] * xv[k] - ov[k] * xjj;
+              rv[k] = ok ? v : 0.0;
+              a.R32[row * a.ldr + col] = (float)rv[k];
+              sq += rv[k] * rv[k];
+              sqx += ok ? xv[k] * xv[k] : 0.0;
+            }
+            if (a.Rt) {  // uniform: the FP16 path writes R in low precision in a separate pass
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                u16 o[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o[e] = to_lp<F16>((float)(rv[4 * q + e] * a.lp_scale));
+                uint2 v;
+                v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
+                v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
+                *(uint2*)((u16*)a.Rt + pb_index(col, rbase + 8 * q, a.ldrt)) = v;
+              }
+            }
+          } else {  // kLpEpCorr: X <- X + D_X R + alpha acc (exact zeros above the diagonal)
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+              const int64_t row = rbase + 8 * (k >> 2) + (k & 3);
+              const double v = xv[k] + dv[k] * ov[k] + alpha * (double)blk[k];
+              a.X[row * a.ldx + col] = col <= row ? v : 0.0;
+            }
+          }
+          return;
+        }
+        // Edge tile: gather the block's FP64 / FP32 operands first, all loads
         // unconditional (out-of-triangle lanes read element 0 and discard
         // it), so that they are in flight together; then compute and store.
-        const bool colok = full || col < N;
-        const int64_t rbase = m0 + wm * 128 + i * 32 + 4 * (lane >> 5);
+        const bool colok = col < N;
         double xv[16], dv[16], ov[16];
         bool okv[16];
 #pragma unroll
