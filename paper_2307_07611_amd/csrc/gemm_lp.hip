@@ -34,7 +34,7 @@ template <int NSPLIT>
 struct LpShape {
   static constexpr int KT = NSPLIT == 1 ? 32 : 16;  // K per LDS stage
   static constexpr int NT = NSPLIT == 1 ? 2 : 4;    // staged tiles per stage
-  static constexpr int NBUF = 4;                    // LDS stages: loads run NBUF - 1 stages ahead
+  static constexpr int NBUF = 5;                    // LDS stages (160 KB): loads run NBUF - 1 stages ahead
   static constexpr int CPR = KT / 8;                // 16-byte chunks per tile row
   static constexpr int TILE = LT * KT;              // elements of one staged tile (no padding)
   static constexpr int RPI = 512 / KT;              // tile rows per 1 KB direct-load instruction
@@ -127,8 +127,9 @@ template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, in
 __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   typedef LpShape<NSPLIT> S;
   constexpr int KT = S::KT;
-  extern __shared__ __attribute__((aligned(16))) u16 lds[];  // NBUF stages x NT tiles x TILE elements
-  __shared__ double red[2][4];
+  // NBUF stages x NT tiles x TILE elements (all of the CU's LDS); after the
+  // main loop its first bytes hold the per-wave partial sums of the residual
+  extern __shared__ __attribute__((aligned(16))) u16 lds[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
@@ -588,6 +589,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
     }
   }
   if (EPI == kLpEpResid) {
+    double(*red)[4] = (double(*)[4])lds;  // free: every wave has left the main loop (its last barrier)
     for (int m = 32; m >= 1; m >>= 1) {
       sq += __shfl_xor(sq, m, 64);
       sqx += __shfl_xor(sqx, m, 64);
