@@ -98,7 +98,16 @@ struct SplitOut {
   int64_t ldo;
   unsigned short *hi_b, *lo_b, *hi_tb, *lo_tb;
   int64_t kb;
+  // optional, one double per 64 x 64 tile of the lower triangle (split_tiles):
+  // the sum of squares of the values read (lower triangle, diagonal included,
+  // before scaling) and of the diagonal values alone
+  double *sq, *dsq;
 };
+// Tiles (workgroups) of one split of order n.
+inline int64_t split_tiles(int64_t n) {
+  const int64_t t = (n + 63) / 64;
+  return t * (t + 1) / 2;
+}
 
 // Low-precision slices of a lower-triangular FP64 matrix times a power-of-two
 // scale (64 x 64 tiles of the lower triangle; elements above the diagonal are

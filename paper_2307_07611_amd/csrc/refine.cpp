@@ -47,7 +47,7 @@ struct WsRefine {
   // hi(N_X); B roles hi/lo(N_X)^T and R^T
   unsigned short *PLhi, *PLlo, *PX, *PXthi, *PXtlo, *PRt;
   float* R32;
-  double *dL, *dX, *tile_sq, *tile_sqx, *partial, *scal;
+  double *dL, *dX, *tile_sq, *tile_sqx, *partial, *scal, *split_sq, *split_dsq;
   int64_t ldp, kb;
 };
 
@@ -76,6 +76,8 @@ WsRefine carve_refine(Carve& c, int64_t n, int64_t leaf) {
   w.tile_sq = c.take<double>((size_t)nt);
   w.tile_sqx = c.take<double>((size_t)nt);
   w.partial = c.take<double>(kPart);
+  w.split_sq = c.take<double>((size_t)split_tiles(n));
+  w.split_dsq = c.take<double>((size_t)split_tiles(n));
   w.scal = c.take<double>(8);
   return w;
 }
@@ -211,8 +213,13 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     so.hi_b = w.PLhi;  // panel-blocked hi / lo for the residual
     so.lo_b = w.PLlo;
     so.kb = w.kb;
+    so.sq = w.split_sq;  // ||tril(L)||^2 and the diagonal's part, per tile
+    so.dsq = w.split_dsq;
     HIP_TRY(launch_split(L, ldl, n, f16, so, w.dL, o.unit_diag, 1, sL, s));
   }
+  // ||tril(L)||^2 and sum of diag(L)^2 (L is read once, by the split)
+  HIP_TRY(launch_reduce_sum(w.split_sq, split_tiles(n), w.scal + 2, s));
+  HIP_TRY(launch_reduce_sum(w.split_dsq, split_tiles(n), w.scal + 3, s));
   if (f16) {
     std::vector<double> d((size_t)n);
     HIP_TRY(hipMemcpyAsync(d.data(), w.dL, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -228,9 +235,6 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
                                 w.status, 0, s));
   }
   HIP_TRY(lp_levels(n, X, ldx, leaf, f16, w, sL, sXf, s));
-  // ||tril(L)||^2 and sum of diag(L)^2 once
-  HIP_TRY(launch_sumsq<double>(L, n, ldl, 1, o.unit_diag, w.partial, kPart, w.scal + 2, s));
-  HIP_TRY(launch_sumsq_vec(w.dL, n, w.scal + 3, s));
 
   GemmBatch bt{1, 1, n, n, n, n, n, n};
   int iter = 0;
@@ -261,11 +265,15 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       so.hi_tb = w.PXthi;  // B role of the residual
       so.lo_tb = w.PXtlo;
       so.kb = w.kb;
+      if (resid_fp64 < 0) {  // the norms of X for the precision decision, from the split's read
+        so.sq = w.split_sq;
+        so.dsq = w.split_dsq;
+      }
       HIP_TRY(launch_split(X, ldx, n, f16, so, w.dX, 0, 1, sX, s));
     }
     if (resid_fp64 < 0) {
-      HIP_TRY(launch_sumsq<double>(X, n, ldx, 1, 0, w.partial, kPart, w.scal + 4, s));
-      HIP_TRY(launch_sumsq_vec(w.dX, n, w.scal + 5, s));
+      HIP_TRY(launch_reduce_sum(w.split_sq, split_tiles(n), w.scal + 4, s));
+      HIP_TRY(launch_reduce_sum(w.split_dsq, split_tiles(n), w.scal + 5, s));
       double h6[6];
       HIP_TRY(hipMemcpyAsync(h6, w.scal, sizeof(h6), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));

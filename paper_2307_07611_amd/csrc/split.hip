@@ -45,6 +45,7 @@ __global__ __launch_bounds__(256) void k_split(const TS* __restrict__ S, int64_t
                                                double* __restrict__ diag, int unit, int strict, double scale) {
   __shared__ u16 th[64][66];
   __shared__ u16 tl[64][66];
+  __shared__ double red[2][4];
   const int64_t q = blockIdx.x;
   int64_t it = (int64_t)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
   while (it * (it + 1) / 2 > q) --it;
@@ -52,12 +53,15 @@ __global__ __launch_bounds__(256) void k_split(const TS* __restrict__ S, int64_t
   const int64_t jt = q - it * (it + 1) / 2;
   const int64_t i0 = it * 64, j0 = jt * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  double sq = 0.0, dsq = 0.0;
   for (int r = ty; r < 64; r += 4) {
     const int64_t i = i0 + r, j = j0 + tx;
     u16 h = 0, l = 0;
     if (i < n && j < n) {
       double v = (j <= i) ? (double)S[i * lds + j] : 0.0;
       if (unit && i == j) v = 1.0;
+      sq += v * v;
+      dsq += (i == j) ? v * v : 0.0;
       if (i == j && diag) diag[i] = v;
       if (strict && i == j) v = 0.0;  // slices of the strictly lower part
       v *= scale;
@@ -70,6 +74,21 @@ __global__ __launch_bounds__(256) void k_split(const TS* __restrict__ S, int64_t
     }
     th[r][tx] = h;
     tl[r][tx] = l;
+  }
+  if (o.sq) {  // uniform: this tile's sums of squares (fixed order)
+    for (int m = 32; m >= 1; m >>= 1) {
+      sq += __shfl_xor(sq, m, 64);
+      dsq += __shfl_xor(dsq, m, 64);
+    }
+    if (tx == 0) {
+      red[0][ty] = sq;
+      red[1][ty] = dsq;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      o.sq[q] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+      o.dsq[q] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    }
   }
   const bool rm_t = o.hi_t || o.lo_t;
   const bool pb = o.hi_b || o.lo_b || o.hi_tb || o.lo_tb;
@@ -107,7 +126,8 @@ template <typename TS>
 static hipError_t split_t(const TS* S, int64_t lds, int64_t n, int f16, const SplitOut& o, double* diag, int unit,
                           int strict, double scale, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const int64_t T = (n + 63) / 64, blocks = T * (T + 1) / 2;
+  if (o.sq && !o.dsq) return hipErrorInvalidValue;
+  const int64_t blocks = split_tiles(n);
   if (f16)
     hipLaunchKernelGGL((k_split<1, TS>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, o, diag, unit, strict,
                        scale);
