@@ -3,89 +3,143 @@
 // CRIT, transposed to the lower case):
 //     X(j,j) = 1 / L(j,j),
 //     X(i,j) = -( sum_{k=j}^{i-1} L(i,k) X(k,j) ) / L(i,i),   i > j.
-// Rows are produced in order i = 1, 2, ...; all columns j < i of row i are
-// computed at once, one column per group of P lanes (P = 256 / b), the P
-// lanes splitting the k-sum and combining it with cross-lane shuffles. L and
-// X live in LDS in packed lower storage (row i at offset i(i+1)/2), so a
-// 128 x 128 FP64 leaf needs 2 x 66 KB of the 160 KB LDS.
+// X is held in registers and built right-looking, one pivot row at a time
+// (see k_leaf_inverse); L^T of the leaf sits in LDS (a 128 x 128 FP64 leaf
+// takes 130 KB of the 160 KB).
 #include "common.h"
 #include "launch.h"
 
 namespace trinv {
 
-template <typename T>
-__device__ __forceinline__ T shfl_xor_t(T v, int mask) {
-  return __shfl_xor(v, mask, 64);
-}
-
 // grid: (leaves per matrix, batch). Matrix `bz` starts at element bz*stride.
 // Leaf l covers rows/cols [l*b, min(n, l*b + b)).
+//
+// Thread (ty, tx) of a 16 x 16 grid owns the elements (ty + 16 a, tx + 16 c),
+// a, c < B / 16, of the leaf's X in registers; column p of L is read from an
+// LDS copy of L^T. Pivot p = 16 P + q, in order:
+//   the owners of row p divide it by L(p, p): X(p, :) final, broadcast through
+//   LDS (double buffered, one barrier per pivot);
+//   every row i > p takes X(i, :) -= L(i, p) X(p, :).
+// Starting from X = I this gives X(i, j) = -(sum_{k=j}^{i-1} L(i, k) X(k, j))
+// / L(i, i), the sums taken in ascending k, as the column recurrence forms them.
+template <typename T, int B, int P>
+__device__ __forceinline__ void leaf_phase(T (&v)[B / 16][B / 16], int bs, int tx, int ty, const T* __restrict__ Lt,
+                                           T* __restrict__ rowb, int unit, int64_t r0, int64_t* first_bad) {
+  constexpr int NS = B / 16, LS = B + 1;
+  for (int q = 0; q < 16; ++q) {
+    const int p = 16 * P + q;
+    if (p >= bs) return;
+    T* rb = rowb + (p & 1) * B;
+    if (ty == q) {
+      const T d = unit ? T(1) : Lt[p * LS + p];
+#pragma unroll
+      for (int c = 0; c <= P; ++c) {
+        if (tx + 16 * c <= p) v[P][c] = v[P][c] / d;  // right of the diagonal stays an exact 0
+        rb[tx + 16 * c] = v[P][c];
+      }
+      if (tx == q && !unit && d == T(0) && first_bad)
+        atomicMin((unsigned long long*)first_bad, (unsigned long long)(r0 + p + 1));
+    }
+    __syncthreads();
+    T l[NS], x[NS];
+#pragma unroll
+    for (int a = P; a < NS; ++a) l[a] = Lt[p * LS + ty + 16 * a];
+#pragma unroll
+    for (int c = 0; c <= P; ++c) x[c] = rb[tx + 16 * c];
+#pragma unroll
+    for (int a = P; a < NS; ++a) {
+      const bool below = a > P || ty > q;
+#pragma unroll
+      for (int c = 0; c <= P; ++c) v[a][c] = below ? v[a][c] - l[a] * x[c] : v[a][c];
+    }
+  }
+}
+
 template <typename T, typename TL, int B>
 __global__ __launch_bounds__(256) void k_leaf_inverse(int64_t n, const T* __restrict__ L, int64_t ldl,
                                                       T* __restrict__ X, int64_t ldx, int64_t stride,
                                                       int unit, TL* __restrict__ Xlp, TL* __restrict__ Xlpt,
                                                       int64_t ldxl, double lp_scale, int64_t* __restrict__ first_bad,
                                                       int per_matrix_status) {
-  constexpr int P = 256 / B;  // lanes per column
-  constexpr int PACK = B * (B + 1) / 2;
-  __shared__ T Lp[PACK];
-  __shared__ T Xp[PACK];
-
-  const int tid = threadIdx.x;
+  constexpr int NS = B / 16, LS = B + 1;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  T* Lt = (T*)smem;           // L^T of the leaf: Lt[k * LS + i] = L(i, k), zero outside
+  T* rowb = Lt + B * LS;      // two broadcast rows
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * B;
   const int bs = (int)imin64(B, n - r0);
   if (bs <= 0) return;
   const T* Lb = L + (int64_t)blockIdx.y * stride + r0 * ldl + r0;
   T* Xb = X + (int64_t)blockIdx.y * stride + r0 * ldx + r0;
+  int64_t* fb = first_bad ? first_bad + (per_matrix_status ? blockIdx.y : 0) : nullptr;
 
-  // Stage the lower triangle of the leaf in LDS (row-major reads, coalesced).
-  for (int idx = tid; idx < bs * bs; idx += 256) {
-    const int i = idx / bs, j = idx % bs;
-    if (j <= i) Lp[i * (i + 1) / 2 + j] = Lb[(int64_t)i * ldl + j];
+  // Stage L^T (row-major reads, coalesced); the strict upper part of L is not read.
+  for (int idx = tid; idx < B * B; idx += 256) {
+    const int i = idx / B, k = idx % B;
+    Lt[k * LS + i] = (i < bs && k <= i) ? Lb[(int64_t)i * ldl + k] : T(0);
   }
-  __syncthreads();
-
-  // Diagonal: X(i,i) = 1 / L(i,i); report the first exact zero pivot.
-  if (tid < bs) {
-    const T d = Lp[tid * (tid + 1) / 2 + tid];
-    if (!unit && d == (T)0 && first_bad)
-      atomicMin((unsigned long long*)(first_bad + (per_matrix_status ? blockIdx.y : 0)),
-                (unsigned long long)(r0 + tid + 1));
-    Xp[tid * (tid + 1) / 2 + tid] = unit ? (T)1 : (T)1 / d;
-  }
-  __syncthreads();
-
-  const int j = tid / P;  // column handled by this lane group
-  const int p = tid % P;  // part of the k-sum
-  for (int i = 1; i < bs; ++i) {
-    const int ri = i * (i + 1) / 2;
-    T s = (T)0;
-    if (j < i) {
-      // k runs over [j, i); lanes of a group take k = j+p, j+p+P, ...
-      for (int k = j + p; k < i; k += P) s += Lp[ri + k] * Xp[k * (k + 1) / 2 + j];
-    }
+  T v[NS][NS];
 #pragma unroll
-    for (int m = 1; m < P; m <<= 1) s += shfl_xor_t(s, m);
-    if (j < i && p == 0) Xp[ri + j] = unit ? -s : -s / Lp[ri + i];
-    __syncthreads();
+  for (int a = 0; a < NS; ++a)
+#pragma unroll
+    for (int c = 0; c < NS; ++c) v[a][c] = (ty + 16 * a == tx + 16 * c) ? T(1) : T(0);
+  __syncthreads();
+  leaf_phase<T, B, 0>(v, bs, tx, ty, Lt, rowb, unit, r0, fb);
+  if constexpr (NS > 1) leaf_phase<T, B, 1>(v, bs, tx, ty, Lt, rowb, unit, r0, fb);
+  if constexpr (NS > 2) {
+    leaf_phase<T, B, 2>(v, bs, tx, ty, Lt, rowb, unit, r0, fb);
+    leaf_phase<T, B, 3>(v, bs, tx, ty, Lt, rowb, unit, r0, fb);
+  }
+  if constexpr (NS > 4) {
+    leaf_phase<T, B, 4>(v, bs, tx, ty, Lt, rowb, unit, r0, fb);
+    leaf_phase<T, B, 5>(v, bs, tx, ty, Lt, rowb, unit, r0, fb);
+    leaf_phase<T, B, 6>(v, bs, tx, ty, Lt, rowb, unit, r0, fb);
+    leaf_phase<T, B, 7>(v, bs, tx, ty, Lt, rowb, unit, r0, fb);
   }
 
-  // Write the full leaf block of X (zeros above the diagonal).
-  for (int idx = tid; idx < bs * bs; idx += 256) {
-    const int i = idx / bs, jj = idx % bs;
-    const T v = (jj <= i) ? Xp[i * (i + 1) / 2 + jj] : (T)0;
-    Xb[(int64_t)i * ldx + jj] = v;
-    if (Xlp) Xlp[(int64_t)blockIdx.y * stride + (r0 + i) * ldxl + r0 + jj] = (TL)(float)((double)v * lp_scale);
-  }
-  // Transposed low-precision copy: element (i, jj) of the leaf at [jj][i],
-  // written with consecutive threads along i (coalesced).
+  // Write the full leaf block of X (exact zeros above the diagonal) and the
+  // optional row-major low-precision copy.
+#pragma unroll
+  for (int a = 0; a < NS; ++a)
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+      const int i = ty + 16 * a, jj = tx + 16 * c;
+      if (i < bs && jj < bs) {
+        Xb[(int64_t)i * ldx + jj] = v[a][c];
+        if (Xlp) Xlp[(int64_t)blockIdx.y * stride + (r0 + i) * ldxl + r0 + jj] = (TL)(float)((double)v[a][c] * lp_scale);
+      }
+    }
+  // Transposed low-precision copy, staged through LDS so that consecutive
+  // threads write consecutive elements.
   if (Xlpt) {
+    __syncthreads();  // every wave is done with Lt
+#pragma unroll
+    for (int a = 0; a < NS; ++a)
+#pragma unroll
+      for (int c = 0; c < NS; ++c) Lt[(tx + 16 * c) * LS + ty + 16 * a] = v[a][c];
+    __syncthreads();
     for (int idx = tid; idx < bs * bs; idx += 256) {
       const int jj = idx / bs, i = idx % bs;
-      const T v = (jj <= i) ? Xp[i * (i + 1) / 2 + jj] : (T)0;
-      Xlpt[(int64_t)blockIdx.y * stride + (r0 + jj) * ldxl + r0 + i] = (TL)(float)((double)v * lp_scale);
+      Xlpt[(int64_t)blockIdx.y * stride + (r0 + jj) * ldxl + r0 + i] = (TL)(float)((double)Lt[jj * LS + i] * lp_scale);
     }
   }
+}
+
+template <typename T, typename TL, int B>
+static hipError_t go_leaf(dim3 grid, hipStream_t s, int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx,
+                          int64_t stride, int unit, TL* Xlp, TL* Xlpt, int64_t ldxl, double lp_scale, int64_t* fb,
+                          int per_matrix_status) {
+  const size_t lds = sizeof(T) * ((size_t)B * (B + 1) + 2 * B);
+  auto k = k_leaf_inverse<T, TL, B>;
+  static bool attr_set = false;  // per instantiation
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k, grid, dim3(256), lds, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb,
+                     per_matrix_status);
+  return hipGetLastError();
 }
 
 template <typename T, typename TL>
@@ -94,16 +148,15 @@ static hipError_t launch_leaf_t(int64_t n, const T* L, int64_t ldl, T* X, int64_
                                 uint64_t* first_bad, int per_matrix_status, hipStream_t s) {
   const int64_t nleaves = (n + leaf - 1) / leaf;
   if (nleaves <= 0 || batch <= 0) return hipSuccess;
-  dim3 grid((unsigned)nleaves, (unsigned)batch), block(256);
+  dim3 grid((unsigned)nleaves, (unsigned)batch);
   int64_t* fb = (int64_t*)first_bad;
   switch (leaf) {
-    case 16: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 16>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status); break;
-    case 32: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 32>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status); break;
-    case 64: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 64>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status); break;
-    case 128: hipLaunchKernelGGL((k_leaf_inverse<T, TL, 128>), grid, block, 0, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status); break;
+    case 16: return go_leaf<T, TL, 16>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status);
+    case 32: return go_leaf<T, TL, 32>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status);
+    case 64: return go_leaf<T, TL, 64>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status);
+    case 128: return go_leaf<T, TL, 128>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <typename T>
