@@ -36,6 +36,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n16384.md")
 KERNEL_SOURCES = {
     "bf16": ["paper_2307_07611_amd/csrc/gemm_lp.hip", "paper_2307_07611_amd/csrc/lowp.h",
              "paper_2307_07611_amd/csrc/common.h"],
+    "f16": ["paper_2307_07611_amd/csrc/gemm_lp.hip", "paper_2307_07611_amd/csrc/lowp.h",
+            "paper_2307_07611_amd/csrc/common.h"],
     "f64": ["paper_2307_07611_amd/csrc/gemm_fp.hip", "paper_2307_07611_amd/csrc/launch.h",
             "paper_2307_07611_amd/csrc/common.h"],
 }
