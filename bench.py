@@ -316,7 +316,7 @@ def main():
                     help="only run a plain copy kernel of this size (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "runs on one GPU: --gpus must be 1 "
                                    "(the multi-GPU sharding is a design note, not code)"}), flush=True)
         sys.exit(2)
 

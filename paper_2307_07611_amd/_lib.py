@@ -56,8 +56,8 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise OSError(f"{LIB_PATH} not found: build it with paper_2307_07611_amd/build.py "
-                      "(or __graft_entry__.build()); there is no CPU fallback")
+        raise OSError(f"{LIB_PATH} not found: build it with paper_2307_07611_amd/build.py; "
+                      "there is no CPU fallback")
     lib = ctypes.CDLL(LIB_PATH)
     lib.trinv_default_opts.argtypes = [ctypes.POINTER(Opts)]
     lib.trinv_default_opts.restype = None
