@@ -498,11 +498,39 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
               }
             }
           } else {  // kLpEpCorr: X <- X + D_X R + alpha acc (exact zeros above the diagonal)
+            double xn[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
               const int64_t row = rbase + 8 * (k >> 2) + (k & 3);
               const double v = xv[k] + dv[k] * ov[k] + alpha * (double)blk[k];
-              a.X[row * a.ldx + col] = col <= row ? v : 0.0;
+              xn[k] = col <= row ? v : 0.0;
+              a.X[row * a.ldx + col] = xn[k];
+            }
+            if constexpr (!F16) {
+              if (a.Xn_tb_hi) {  // uniform: the next residual's slices of the new X, from these values
+                u16 hi[16], lo[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                  const int64_t row = rbase + 8 * (k >> 2) + (k & 3);
+                  const double v = col < row ? xn[k] : 0.0;  // strictly lower part
+                  const __bf16 h = (__bf16)v;
+                  const __bf16 l = (__bf16)(v - (double)(float)h);
+                  hi[k] = __builtin_bit_cast(u16, h);
+                  lo[k] = __builtin_bit_cast(u16, l);
+                  if (row == col) a.dXn[row] = xn[k];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {  // B role: (col, rows row0 .. row0 + 3), 8 contiguous bytes
+                  const int64_t e = pb_index(col, rbase + 8 * q, a.kbx);
+                  uint2 vh, vl;
+                  vh.x = (unsigned)hi[4 * q] | ((unsigned)hi[4 * q + 1] << 16);
+                  vh.y = (unsigned)hi[4 * q + 2] | ((unsigned)hi[4 * q + 3] << 16);
+                  vl.x = (unsigned)lo[4 * q] | ((unsigned)lo[4 * q + 1] << 16);
+                  vl.y = (unsigned)lo[4 * q + 2] | ((unsigned)lo[4 * q + 3] << 16);
+                  *(uint2*)((u16*)a.Xn_tb_hi + e) = vh;
+                  *(uint2*)((u16*)a.Xn_tb_lo + e) = vl;
+                }
+              }
             }
           }
           return;

@@ -59,6 +59,14 @@ struct LpGemmArgs {
   // precision (kLpEpX21 copies, kLpEpResid's Rt); the accumulator itself is
   // scaled by alpha in every epilogue.
   double lp_scale;
+  // kLpEpCorr, BF16, interior tiles only (optional): the slices of the updated
+  // X that the next residual reads, as the split would write them (strictly
+  // lower part, hi / lo in the transposed B role, panel-blocked with kbx K
+  // blocks), and its FP64 diagonal (dXn). Neither may be read by the same call.
+  void* Xn_tb_hi;
+  void* Xn_tb_lo;
+  double* dXn;
+  int64_t kbx;
 };
 
 struct LpConfig {

@@ -47,7 +47,7 @@ struct WsRefine {
   // hi(N_X); B roles hi/lo(N_X)^T and R^T
   unsigned short *PLhi, *PLlo, *PX, *PXthi, *PXtlo, *PRt;
   float* R32;
-  double *dL, *dX, *tile_sq, *tile_sqx, *partial, *scal, *split_sq, *split_dsq;
+  double *dL, *dX, *dX2, *tile_sq, *tile_sqx, *partial, *scal, *split_sq, *split_dsq;
   int64_t ldp, kb;
 };
 
@@ -71,6 +71,7 @@ WsRefine carve_refine(Carve& c, int64_t n, int64_t leaf) {
   w.R32 = c.take<float>((size_t)n * n);
   w.dL = c.take<double>((size_t)n);
   w.dX = c.take<double>((size_t)n);
+  w.dX2 = c.take<double>((size_t)n);
   GemmBatch bt{1, 1, n, n, n, n, n, n};
   const int64_t nt = std::max<int64_t>({1, gemm_lp_tiles(bt, kLowerTiles), gemm_tiles(bt, kLowerTiles)});
   w.tile_sq = c.take<double>((size_t)nt);
@@ -249,6 +250,11 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   int resid_fp64 = -1;  // decided once, after the forward, from the norms
   double floor_est = 0.0;
   const double eps_split = f16 ? std::ldexp(1.0, -22) : std::ldexp(1.0, -16);
+  // diag(X) in use and the spare buffer a fused correction writes the next
+  // one into (it reads the current one).
+  double *dx = w.dX, *dx_next = w.dX2;
+  bool x_sliced = false;  // B-role slices and diagonal of the current X written by the correction
+  bool px_stale = false;  // the A-role slice (read by the correction only) lags behind X
   for (;;) {
     // residual of the current X
     double sX = 1.0;
@@ -258,7 +264,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       HIP_TRY(read_scalar(w.scal + 6, &mx, s));
       sX = pow2_scale(mx, 14);
     }
-    {
+    if (!x_sliced) {
       ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + 6), s);
       SplitOut so{};
       so.hi_b = w.PX;  // A role of the correction
@@ -269,7 +275,8 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
         so.sq = w.split_sq;
         so.dsq = w.split_dsq;
       }
-      HIP_TRY(launch_split(X, ldx, n, f16, so, w.dX, 0, 1, sX, s));
+      HIP_TRY(launch_split(X, ldx, n, f16, so, dx, 0, 1, sX, s));
+      px_stale = false;
     }
     if (resid_fp64 < 0) {
       HIP_TRY(launch_reduce_sum(w.split_sq, split_tiles(n), w.scal + 4, s));
@@ -299,7 +306,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       gf.Xfull = X;
       gf.ldx = ldx;
       gf.dL = w.dL;
-      gf.dX = w.dX;
+      gf.dX = dx;
       gf.R32 = w.R32;
       gf.ldr = n;
       gf.Rt = nullptr;  // R^T for the correction is cast from R32 below
@@ -330,7 +337,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gr.L = L;
     gr.ldl = ldl;
     gr.dL = w.dL;
-    gr.dX = w.dX;
+    gr.dX = dx;
     gr.R32 = w.R32;
     gr.ldr = n;
     gr.Rt = f16 ? nullptr : w.PRt;  // FP16: written below, once ||R|| is known
@@ -377,6 +384,14 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       ProfLaunch pl("split", 0.0, dn * dn / 2 * (4 + 2), s);
       HIP_TRY(launch_split_f32(w.R32, n, n, f16, so, sR, s));
     }
+    if (px_stale) {  // a second correction after a fused one: the A-role slice of X
+      ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + 2), s);
+      SplitOut so{};
+      so.hi_b = w.PX;
+      so.kb = w.kb;
+      HIP_TRY(launch_split(X, ldx, n, f16, so, nullptr, 0, 1, sX, s));
+      px_stale = false;
+    }
     // correction: X <- X + D_X R + N_X R
     LpGemmArgs gc{};
     gc.A_hi = w.PX;
@@ -388,14 +403,27 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gc.lp_scale = 1.0;
     gc.X = X;
     gc.ldx = ldx;
-    gc.dX = w.dX;
+    gc.dX = dx;
     gc.R32 = w.R32;
     gc.ldr = n;
+    // BF16 with interior tiles only: the correction also writes the slices of
+    // the new X for the next residual (the split would re-read all of X)
+    const bool fuse = !f16 && !resid_fp64 && n % 256 == 0;
+    if (fuse) {
+      gc.Xn_tb_hi = w.PXthi;  // read by the residual only, not by the correction
+      gc.Xn_tb_lo = w.PXtlo;
+      gc.dXn = dx_next;
+      gc.kbx = w.kb;
+    }
     LpConfig cc{f16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpCorr};
     {
-      ProfLaunch pl(f16 ? "f16_correction" : "bf16_correction", tri_flops(dn) + dn * dn, dn * dn / 2 * (2 + 2 + 4 + 16), s);
+      ProfLaunch pl(f16 ? "f16_correction" : "bf16_correction", tri_flops(dn) + dn * dn,
+                    dn * dn / 2 * (2 + 2 + 4 + 16 + (fuse ? 4 : 0)), s);
       HIP_TRY(launch_gemm_lp(gc, cc, s));
     }
+    if (fuse) std::swap(dx, dx_next);
+    x_sliced = fuse;
+    px_stale = fuse;
     ++iter;
   }
 }

@@ -132,3 +132,38 @@ def test_refine_n16384_configuration(trinv, mode):
     Xo = oracle.tril_inverse_columns(L, cols)
     Xg = host(X[:, torch.from_numpy(cols).cuda()])
     assert rel_fro(Xg, Xo) < 1e-10
+
+
+def test_bf16_n16384_leaf32_more_corrections(trinv):
+    """Configuration size with 32-wide FP64 leaves: more BF16 levels leave a
+    larger first residual, so the path may need a second correction after one
+    whose epilogue wrote the next residual's slices of X itself (the A-role
+    slice is then re-split from X). Whatever the count, the certified residual
+    must hold under the FP64 check and sampled columns must match the oracle."""
+    import torch
+
+    n = 16384
+    banner(f"bf16_refine n={n} leaf=32 seed=5")
+    L = synth.lower_triangular(n, 5)
+    Ld = dev(L)
+    X, info = run(trinv, Ld, "bf16_refine", leaf=32)
+    r = trinv.residual(Ld, X)
+    print(f"n={n} leaf=32: iterations={info['iterations']} rho_gpu={info['rel_residual']:.3e} "
+          f"rho_fp64={r['rel']:.3e}", flush=True)
+    assert r["rel"] <= 1e-12 and info["rel_residual"] <= 1e-12
+    assert abs(r["rel"] - info["rel_residual"]) <= 0.1 * r["rel"] + 1e-14
+    cols = np.array([1, 5000, 12345])
+    Xo = oracle.tril_inverse_columns(L, cols)
+    Xg = host(X[:, torch.from_numpy(cols).cuda()])
+    assert rel_fro(Xg, Xo) < 1e-10
+    # a tolerance just under what one correction reached: a further correction
+    # runs (with the BF16 residual while its floor allows it)
+    tol = 0.9 * info["rel_residual"]
+    X2, info2 = run(trinv, Ld, "bf16_refine", leaf=32, tol=tol, max_iter=4)
+    r2 = trinv.residual(Ld, X2)
+    print(f"n={n} leaf=32 tol={tol:.3e}: iterations={info2['iterations']} rho_gpu={info2['rel_residual']:.3e} "
+          f"rho_fp64={r2['rel']:.3e} floor={info2['resid_error_bound']:.3e}", flush=True)
+    assert info2["iterations"] >= 2
+    assert r2["rel"] <= tol and info2["rel_residual"] <= tol
+    Xg2 = host(X2[:, torch.from_numpy(cols).cuda()])
+    assert rel_fro(Xg2, Xo) < 1e-10
