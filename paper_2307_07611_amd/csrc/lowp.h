@@ -129,10 +129,11 @@ hipError_t launch_split(const double* S, int64_t lds, int64_t n, int f16, const 
 hipError_t launch_split_f32(const float* S, int64_t lds, int64_t n, int f16, const SplitOut& o, double scale,
                             hipStream_t s);
 // Zeros in a band of `band` columns (multiple of 8) beside the tiles the split
-// writes, in a panel-blocked plane: to the right of each 64-row strip's
-// diagonal tile (right = 1, planes holding a lower triangle) or to its left
-// (right = 0, transposed planes). The refinement products read their operands
-// over block-union K ranges and need these zeros.
-hipError_t launch_zero_band_pb(void* P, int64_t kb, int64_t n, int64_t band, int right, hipStream_t s);
+// writes, in `count` (<= 8) panel-blocked planes in one launch: to the right
+// of each 64-row strip's diagonal tile (right[i] = 1, planes holding a lower
+// triangle) or to its left (right[i] = 0, transposed planes). The refinement
+// products read their operands over block-union K ranges and need these zeros.
+hipError_t launch_zero_band_pb(void* const* planes, const int* right, int count, int64_t kb, int64_t n, int64_t band,
+                               hipStream_t s);
 
 }  // namespace trinv

@@ -191,8 +191,11 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   // The residual and correction products read their operands over block-union
   // K ranges, up to kBand columns past the tiles the splits and epilogues
   // write: those bands must hold zeros (nothing writes them afterwards).
-  for (unsigned short* p : {w.PLhi, w.PLlo, w.PX}) HIP_TRY(launch_zero_band_pb(p, w.kb, n, kBand, 1, s));
-  for (unsigned short* p : {w.PXthi, w.PXtlo, w.PRt}) HIP_TRY(launch_zero_band_pb(p, w.kb, n, kBand, 0, s));
+  {
+    void* planes[6] = {w.PLhi, w.PLlo, w.PX, w.PXthi, w.PXtlo, w.PRt};
+    const int right[6] = {1, 1, 1, 0, 0, 0};
+    HIP_TRY(launch_zero_band_pb(planes, right, 6, w.kb, n, kBand, s));
+  }
   // FP16 planes carry one power-of-two scale each (exact, undone through the
   // epilogues' alpha) so that the values sit in FP16's normal range; BF16 has
   // the exponent range of FP32 and uses 1. L: from max |L|; X during the

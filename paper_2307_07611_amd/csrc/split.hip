@@ -148,13 +148,20 @@ hipError_t launch_split_f32(const float* S, int64_t lds, int64_t n, int f16, con
 }
 
 // Zeros in a band of `band` columns (a multiple of 8) beside the 64 x 64
-// tiles the split writes, in a panel-blocked plane: for rows in 64-row strip
-// q, columns [(q + 1) 64, (q + 1) 64 + band) (right = 1, planes holding a
-// lower triangle) or [q 64 - band, q 64) (right = 0, transposed planes),
-// clipped to [0, 16 kb). One block per strip, 16-byte stores.
-__global__ __launch_bounds__(256) void k_zero_band_pb(u16* __restrict__ P, int64_t kb, int64_t n, int64_t band,
-                                                      int right) {
+// tiles the split writes, in up to 8 panel-blocked planes at once
+// (blockIdx.y selects the plane): for rows in 64-row strip q, columns
+// [(q + 1) 64, (q + 1) 64 + band) (right = 1, planes holding a lower triangle)
+// or [q 64 - band, q 64) (right = 0, transposed planes), clipped to
+// [0, 16 kb). One block per strip and plane, 16-byte stores.
+struct BandPlanes {
+  u16* p[8];
+  int right[8];
+};
+
+__global__ __launch_bounds__(256) void k_zero_band_pb(BandPlanes bp, int64_t kb, int64_t n, int64_t band) {
   const int64_t q = blockIdx.x;
+  u16* P = bp.p[blockIdx.y];
+  const int right = bp.right[blockIdx.y];
   const int64_t c0 = right ? (q + 1) * 64 : q * 64 - band;
   const int64_t lo = c0 < 0 ? 0 : c0, hi = (c0 + band < 16 * kb) ? c0 + band : 16 * kb;
   if (hi <= lo) return;
@@ -165,9 +172,17 @@ __global__ __launch_bounds__(256) void k_zero_band_pb(u16* __restrict__ P, int64
   }
 }
 
-hipError_t launch_zero_band_pb(void* P, int64_t kb, int64_t n, int64_t band, int right, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_band_pb, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, (u16*)P, kb, n, band, right);
+hipError_t launch_zero_band_pb(void* const* planes, const int* right, int count, int64_t kb, int64_t n, int64_t band,
+                               hipStream_t s) {
+  if (n <= 0 || count <= 0) return hipSuccess;
+  if (count > 8) return hipErrorInvalidValue;
+  BandPlanes bp{};
+  for (int i = 0; i < count; ++i) {
+    bp.p[i] = (u16*)planes[i];
+    bp.right[i] = right[i];
+  }
+  hipLaunchKernelGGL(k_zero_band_pb, dim3((unsigned)((n + 63) / 64), (unsigned)count), dim3(256), 0, s, bp, kb, n,
+                     band);
   return hipGetLastError();
 }
 
