@@ -29,7 +29,7 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}
 HBM_PEAK_GBS = 8000.0
 # Library profile classes that are matrix-core products (one class = one kernel
 # instantiation); the leading token is the operand precision.
-MFMA_KINDS = ("level_T", "level_X21", "residual", "correction")
+MFMA_KINDS = ("level_T", "level_X21", "residual", "residual2", "correction")
 # HBM traffic per launch measured with hardware counters, keyed by profile class
 # and by a hash of the kernel sources at the time of the measurement.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n16384.md")

@@ -15,7 +15,9 @@
 //
 // The optional 3-product split forms A_hi B_hi + A_hi B_lo + A_lo B_hi in the
 // same accumulator (an operand v is carried as hi = round(v) plus
-// lo = round(v - hi), which multiplies the precision by the slice width).
+// lo = round(v - hi), which multiplies the precision by the slice width); the
+// 2-product form A_hi B_hi + A_lo B_hi serves a B that its hi slice holds
+// exactly.
 // Rows beyond M (columns beyond N) are clamped to the last valid one: they
 // only feed outputs that are not stored. Zero fill beyond K and the element
 // masks of triangular operands are applied only in K steps that reach the K
@@ -33,7 +35,7 @@ constexpr int LT = 256;  // workgroup tile (rows and columns)
 template <int NSPLIT>
 struct LpShape {
   static constexpr int KT = NSPLIT == 1 ? 32 : 16;  // K per LDS stage
-  static constexpr int NT = NSPLIT == 1 ? 2 : 4;    // staged tiles per stage
+  static constexpr int NT = NSPLIT == 1 ? 2 : (NSPLIT == 2 ? 3 : 4);  // staged tiles per stage
   static constexpr int NBUF = 5;                    // LDS stages (160 KB): loads run NBUF - 1 stages ahead
   static constexpr int CPR = KT / 8;                // 16-byte chunks per tile row
   static constexpr int TILE = LT * KT;              // elements of one staged tile (no padding)
@@ -74,6 +76,12 @@ template <int F16>
 __device__ __forceinline__ u16 to_lp(float v) {
   if (F16) return __builtin_bit_cast(u16, (_Float16)v);
   return __builtin_bit_cast(u16, (__bf16)v);
+}
+
+template <int F16>
+__device__ __forceinline__ float lp_to_f32(u16 v) {
+  if (F16) return (float)__builtin_bit_cast(_Float16, v);
+  return (float)__builtin_bit_cast(__bf16, v);
 }
 
 __device__ __forceinline__ int64_t tri_root_lp(int64_t q) {
@@ -137,15 +145,18 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   const int64_t tm = (bt.M + LT - 1) / LT, tn = (bt.N + LT - 1) / LT;
   const int64_t nz = bt.nmerge;
   // L2-aware schedule: tiles are grouped in GB x GB blocks run by 16
-  // consecutive workgroups of one XCD (block B on XCD B % 8; workgroups are
-  // dispatched round-robin over the 8 XCDs), so a block's tiles share GB row
-  // panels and GB column panels in that XCD's L2. Blocks are taken heaviest
-  // first; there are enough of them to keep the XCDs balanced.
+  // consecutive workgroups of one XCD (workgroups are dispatched round-robin
+  // over the 8 XCDs), so a block's tiles share GB row panels and GB column
+  // panels in that XCD's L2. Blocks are taken heaviest first, eight per round,
+  // and the rounds alternate direction over the XCDs (round r gives block
+  // 8r + x to XCD x when r is even, 8r + 7 - x when odd), so that no XCD
+  // receives the heaviest block of every round.
   constexpr int GB = 4;
   const int64_t bm = (tm + GB - 1) / GB, bn = (tn + GB - 1) / GB;
   const int64_t nblk = (TILES == kLowerTiles) ? nz * bm * (bm + 1) / 2 : nz * bm * bn;
   const int64_t w = blockIdx.x, x = w % kNumXcd, q = w / kNumXcd;
-  const int64_t B = (q / (GB * GB)) * kNumXcd + x;
+  const int64_t round = q / (GB * GB);
+  const int64_t B = round * kNumXcd + ((round & 1) ? kNumXcd - 1 - x : x);
   const int pos = (int)(q % (GB * GB));
   if (B >= nblk) return;
   int64_t z, bi, bj;
@@ -167,9 +178,8 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   }
   int64_t klo = 0, khi = K;
   if (KLO == kLoN0) klo = n0;
-  if (KLO == kLoBlock) klo = bj * GB * LT;
+  if (KLO == kLoN0Pb) klo = n0;
   if (KHI == kHiM1) khi = imin64(K, m0 + LT);
-  if (KHI == kHiBlock) khi = imin64(K, (bi * GB + GB) * LT);
   klo = (klo / KT) * KT;
 
   // Staging by direct global -> LDS loads: instruction i of wave w fills
@@ -180,12 +190,12 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   const u16* tb[4];
   tb[0] = (const u16*)a.A_hi + z * a.a_bstride;
   tb[1] = (const u16*)a.Bt_hi + z * a.b_bstride;
-  tb[2] = NSPLIT == 3 ? (const u16*)a.A_lo + z * a.a_bstride : nullptr;
+  tb[2] = NSPLIT >= 2 ? (const u16*)a.A_lo + z * a.a_bstride : nullptr;
   tb[3] = NSPLIT == 3 ? (const u16*)a.Bt_lo + z * a.b_bstride : nullptr;
-  // Panel-blocked operands (block-union products): the stage of a tile is
+  // Panel-blocked operands (refinement products): the stage of a tile is
   // KT / 16 consecutive 8 KB blocks of its 256-row panel, copied linearly, so
   // the LDS tile is [KT / 16][256][16] with the plane's half exchange.
-  constexpr bool PB = (KLO == kLoBlock);
+  constexpr bool PB = (KLO == kLoN0Pb);
   uint32_t off[S::NT][S::IPW];  // byte offsets of this lane's source chunk, stage 0
 #pragma unroll
   for (int tt = 0; tt < S::NT; ++tt) {
@@ -309,6 +319,22 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
           }
         }
       }
+    } else if constexpr (NSPLIT == 2) {  // B carried exactly by its hi slice: A_lo B_hi + A_hi B_hi
+      u32x4 ah[4], bh[4], al[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        al[b] = frag(base, 2, 0, b);
+        bh[b] = frag(base, 1, 0, b);
+        ah[b] = frag(base, 0, 0, b);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(al[i], bh[j], acc[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(ah[i], bh[j], acc[i][j]);
     } else {
       u32x4 ah[2][4], bh[2][4], al[2][4], bl[2][4];
 #pragma unroll
@@ -429,7 +455,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
             const double v = alpha * (double)blk[4 * q + e];
             o[e] = to_lp<F16>((float)(v * a.lp_scale));
             if (full || (colok && row < M)) {
-              a.X[z * a.x_bstride + row * a.ldx + col] = v;
+              a.X[z * a.x_bstride + row * a.ldx + col] = a.x_round ? (double)lp_to_f32<F16>(o[e]) / a.lp_scale : v;
               ((u16*)a.Xlp)[z * a.xlp_bstride + row * a.ldxlp + col] = o[e];
             }
           }
@@ -668,16 +694,18 @@ static hipError_t dispatch_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_
   if (c.nsplit == 1 && c.amask == 1 && c.bmask == 0 && c.tiles == kAllTiles && c.order == kRowDesc &&
       c.klo == kLoZero && c.khi == kHiM1 && c.epi == kLpEpX21)
     return go_lp<F16, 1, 1, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kLpEpX21>(a, s, total);
-  // residual and correction over block-union K ranges (operands zero outside
-  // their triangles, no masks)
-  if (c.amask == 0 && c.bmask == 0 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoBlock &&
-      c.khi == kHiBlock) {
+  // residual and correction: lower tiles, each over its own K range, on
+  // panel-blocked planes (zero outside their triangles, no masks)
+  if (c.amask == 0 && c.bmask == 0 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoN0Pb &&
+      c.khi == kHiM1) {
     if (c.epi == kLpEpResid && c.nsplit == 3)
-      return go_lp<F16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpResid>(a, s, total);
+      return go_lp<F16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid>(a, s, total);
+    if (c.epi == kLpEpResid && c.nsplit == 2)
+      return go_lp<F16, 2, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid>(a, s, total);
     if (c.epi == kLpEpResid && c.nsplit == 1)
-      return go_lp<F16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpResid>(a, s, total);
+      return go_lp<F16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid>(a, s, total);
     if (c.epi == kLpEpCorr && c.nsplit == 1)
-      return go_lp<F16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpCorr>(a, s, total);
+      return go_lp<F16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpCorr>(a, s, total);
   }
   return hipErrorInvalidValue;
 }

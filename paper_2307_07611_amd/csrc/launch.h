@@ -13,11 +13,12 @@ namespace trinv {
 // too, row-major / transposed (leading dimension ldxl, same batch stride),
 // of the values times lp_scale (a power of two). first_bad: atomic minimum of
 // the 1-based indices of exact zero pivots (init to all ones); one word for
-// the whole call, or one per matrix (per_matrix_status = 1).
+// the whole call, or one per matrix (per_matrix_status = 1). round_x (needs
+// Xlp): X receives the copy's values (divided by lp_scale) off the diagonal.
 template <typename T>
 hipError_t launch_leaf(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int64_t stride, int64_t batch,
                        int leaf, int unit, void* Xlp, void* Xlpt, int lp_is_f16, int64_t ldxl, double lp_scale,
-                       uint64_t* first_bad, int per_matrix_status, hipStream_t s);
+                       uint64_t* first_bad, int per_matrix_status, hipStream_t s, int round_x = 0);
 
 // ---------------------------------------------------------------- tile products
 // A tile product D = alpha * op(A) * op(B) over a set of output tiles
@@ -26,11 +27,10 @@ hipError_t launch_leaf(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, in
 // tile set and the order in which tiles are dispatched (heaviest first).
 enum KLo { kLoZero = 0, kLoN0 = 1, kLoM0 = 2, kLoMax = 3 };   // k >= 0 | n0 | m0 | max(m0, n0)
 enum KHi { kHiK = 0, kHiM1 = 1, kHiN1 = 2 };                   // k < K | m0 + TM | n0 + TN
-// Low-precision products of lower tiles only: every tile of a tile block
-// takes the block's union range (first column of the block .. last row of the
-// block), so the block's tiles read the same panels at the same time; the
-// operands must hold zeros wherever that range leaves their triangles.
-enum { kLoBlock = 4, kHiBlock = 3 };
+// Low-precision products of lower tiles over panel-blocked planes, each tile
+// over its own range n0 .. m0 + TM (with kHiM1); the operands must hold zeros
+// wherever that range leaves their triangles.
+enum { kLoN0Pb = 5 };
 enum Tiles { kAllTiles = 0, kLowerTiles = 1 };                  // all tiles | tiles with it >= jt
 enum Order {
   kColAsc = 0,   // all tiles, tile column ascending (work shrinks with the column)

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_leaf_inverse(int64_t n, const T* __rest
                                                       T* __restrict__ X, int64_t ldx, int64_t stride,
                                                       int unit, TL* __restrict__ Xlp, TL* __restrict__ Xlpt,
                                                       int64_t ldxl, double lp_scale, int64_t* __restrict__ first_bad,
-                                                      int per_matrix_status) {
+                                                      int per_matrix_status, int round_x) {
   constexpr int NS = B / 16, LS = B + 1;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   T* Lt = (T*)smem;           // L^T of the leaf: Lt[k * LS + i] = L(i, k), zero outside
@@ -98,15 +98,18 @@ __global__ __launch_bounds__(256) void k_leaf_inverse(int64_t n, const T* __rest
   }
 
   // Write the full leaf block of X (exact zeros above the diagonal) and the
-  // optional row-major low-precision copy.
+  // optional row-major low-precision copy. round_x: the off-diagonal entries
+  // of X are stored as the copy's values (divided by lp_scale), the diagonal
+  // as computed.
 #pragma unroll
   for (int a = 0; a < NS; ++a)
 #pragma unroll
     for (int c = 0; c < NS; ++c) {
       const int i = ty + 16 * a, jj = tx + 16 * c;
       if (i < bs && jj < bs) {
-        Xb[(int64_t)i * ldx + jj] = v[a][c];
-        if (Xlp) Xlp[(int64_t)blockIdx.y * stride + (r0 + i) * ldxl + r0 + jj] = (TL)(float)((double)v[a][c] * lp_scale);
+        const TL lp = (TL)(float)((double)v[a][c] * lp_scale);
+        Xb[(int64_t)i * ldx + jj] = (round_x && i != jj) ? (T)((double)(float)lp / lp_scale) : v[a][c];
+        if (Xlp) Xlp[(int64_t)blockIdx.y * stride + (r0 + i) * ldxl + r0 + jj] = lp;
       }
     }
   // Transposed low-precision copy, staged through LDS so that consecutive
@@ -128,7 +131,7 @@ __global__ __launch_bounds__(256) void k_leaf_inverse(int64_t n, const T* __rest
 template <typename T, typename TL, int B>
 static hipError_t go_leaf(dim3 grid, hipStream_t s, int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx,
                           int64_t stride, int unit, TL* Xlp, TL* Xlpt, int64_t ldxl, double lp_scale, int64_t* fb,
-                          int per_matrix_status) {
+                          int per_matrix_status, int round_x) {
   const size_t lds = sizeof(T) * ((size_t)B * (B + 1) + 2 * B);
   auto k = k_leaf_inverse<T, TL, B>;
   static bool attr_set = false;  // per instantiation
@@ -138,23 +141,23 @@ static hipError_t go_leaf(dim3 grid, hipStream_t s, int64_t n, const T* L, int64
     attr_set = true;
   }
   hipLaunchKernelGGL(k, grid, dim3(256), lds, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb,
-                     per_matrix_status);
+                     per_matrix_status, round_x);
   return hipGetLastError();
 }
 
 template <typename T, typename TL>
 static hipError_t launch_leaf_t(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int64_t stride,
                                 int64_t batch, int leaf, int unit, TL* Xlp, TL* Xlpt, int64_t ldxl, double lp_scale,
-                                uint64_t* first_bad, int per_matrix_status, hipStream_t s) {
+                                uint64_t* first_bad, int per_matrix_status, int round_x, hipStream_t s) {
   const int64_t nleaves = (n + leaf - 1) / leaf;
   if (nleaves <= 0 || batch <= 0) return hipSuccess;
   dim3 grid((unsigned)nleaves, (unsigned)batch);
   int64_t* fb = (int64_t*)first_bad;
   switch (leaf) {
-    case 16: return go_leaf<T, TL, 16>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status);
-    case 32: return go_leaf<T, TL, 32>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status);
-    case 64: return go_leaf<T, TL, 64>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status);
-    case 128: return go_leaf<T, TL, 128>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status);
+    case 16: return go_leaf<T, TL, 16>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x);
+    case 32: return go_leaf<T, TL, 32>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x);
+    case 64: return go_leaf<T, TL, 64>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x);
+    case 128: return go_leaf<T, TL, 128>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x);
     default: return hipErrorInvalidValue;
   }
 }
@@ -162,17 +165,18 @@ static hipError_t launch_leaf_t(int64_t n, const T* L, int64_t ldl, T* X, int64_
 template <typename T>
 hipError_t launch_leaf(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int64_t stride, int64_t batch,
                        int leaf, int unit, void* Xlp, void* Xlpt, int lp_is_f16, int64_t ldxl, double lp_scale,
-                       uint64_t* first_bad, int per_matrix_status, hipStream_t s) {
+                       uint64_t* first_bad, int per_matrix_status, hipStream_t s, int round_x) {
+  if (round_x && !Xlp) return hipErrorInvalidValue;
   if (Xlp && lp_is_f16)
     return launch_leaf_t<T, _Float16>(n, L, ldl, X, ldx, stride, batch, leaf, unit, (_Float16*)Xlp, (_Float16*)Xlpt,
-                                      ldxl, lp_scale, first_bad, per_matrix_status, s);
+                                      ldxl, lp_scale, first_bad, per_matrix_status, round_x, s);
   return launch_leaf_t<T, __bf16>(n, L, ldl, X, ldx, stride, batch, leaf, unit, (__bf16*)Xlp, (__bf16*)Xlpt, ldxl,
-                                  lp_scale, first_bad, per_matrix_status, s);
+                                  lp_scale, first_bad, per_matrix_status, round_x, s);
 }
 
 template hipError_t launch_leaf<double>(int64_t, const double*, int64_t, double*, int64_t, int64_t, int64_t, int,
-                                        int, void*, void*, int, int64_t, double, uint64_t*, int, hipStream_t);
+                                        int, void*, void*, int, int64_t, double, uint64_t*, int, hipStream_t, int);
 template hipError_t launch_leaf<float>(int64_t, const float*, int64_t, float*, int64_t, int64_t, int64_t, int, int,
-                                       void*, void*, int, int64_t, double, uint64_t*, int, hipStream_t);
+                                       void*, void*, int, int64_t, double, uint64_t*, int, hipStream_t, int);
 
 }  // namespace trinv

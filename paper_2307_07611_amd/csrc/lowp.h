@@ -22,10 +22,10 @@ enum LpEpilogue {
 // All operands in element units of their own type. Low-precision operands:
 // A row-major [m][k]; B stored transposed, Bt[n][k] = B(k, n), so both are
 // k-contiguous. Every low-precision buffer must have at least 8 readable
-// padding columns past the last column a product uses. Products over
-// block-union K ranges (klo = kLoBlock) read panel-blocked planes instead, and
-// lda / ldb are then their K blocks per panel; their residual epilogue writes
-// Rt panel-blocked too (ldrt = K blocks per panel).
+// padding columns past the last column a product uses. The refinement
+// products (klo = kLoN0Pb) read panel-blocked planes instead, and lda / ldb
+// are then their K blocks per panel; their residual epilogue writes Rt
+// panel-blocked too (ldrt = K blocks per panel).
 struct LpGemmArgs {
   const void* A_hi;
   const void* A_lo;  // second slice (3-product split) or null
@@ -45,6 +45,7 @@ struct LpGemmArgs {
   int64_t ldxlp, xlp_bstride;
   void* Xlpt;  // kLpEpX21: transposed low-precision copy (element (r,c) -> [c][r])
   int64_t ldxlpt, xlpt_bstride;
+  int x_round;  // kLpEpX21: the FP64 X21 holds the low-precision copy's values (divided by lp_scale)
   const double* L;  // kLpEpResid
   int64_t ldl;
   const double* dL;  // diag(L) (kLpEpResid)
@@ -71,7 +72,7 @@ struct LpGemmArgs {
 
 struct LpConfig {
   int f16;     // 0: BF16, 1: FP16
-  int nsplit;  // 1: hi*hi, 3: hi*hi + hi*lo + lo*hi
+  int nsplit;  // 1: hi*hi, 2: hi*hi + lo*hi (B exact in hi), 3: hi*hi + hi*lo + lo*hi
   int amask, bmask;
   int tiles, order, klo, khi;
   int epi;
@@ -132,7 +133,8 @@ hipError_t launch_split_f32(const float* S, int64_t lds, int64_t n, int f16, con
 // writes, in `count` (<= 8) panel-blocked planes in one launch: to the right
 // of each 64-row strip's diagonal tile (right[i] = 1, planes holding a lower
 // triangle) or to its left (right[i] = 0, transposed planes). The refinement
-// products read their operands over block-union K ranges and need these zeros.
+// products read each panel up to the end of its diagonal 256 x 256 block and
+// need these zeros.
 hipError_t launch_zero_band_pb(void* const* planes, const int* right, int count, int64_t kb, int64_t n, int64_t band,
                                hipStream_t s);
 

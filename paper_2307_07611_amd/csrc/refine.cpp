@@ -28,7 +28,7 @@ namespace trinv {
 namespace {
 
 constexpr int64_t kPart = 4096;
-constexpr int64_t kBand = 1280;  // > (tile block - 1) x tile width + 64
+constexpr int64_t kBand = 256;  // >= product tile (256) - split tile (64)
 
 int64_t lp_ld(int64_t n) { return (n + 8 + 63) / 64 * 64; }
 int64_t t_ld(int64_t hA) { return (hA + 8 + 63) / 64 * 64; }
@@ -87,7 +87,7 @@ WsRefine carve_refine(Carve& c, int64_t n, int64_t leaf) {
 // sL, sX: power-of-two scales of the L and X planes (1 for BF16); T is stored
 // with the scale of X.
 hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, const WsRefine& w, double sL,
-                     double sX, hipStream_t s) {
+                     double sX, int x_round, hipStream_t s) {
   const int64_t ldp = w.ldp;
   for (const Level& lv : levels_of(n, leaf)) {
     const int64_t hA = lv.hA, span = lv.span, ldt = t_ld(hA);
@@ -136,6 +136,7 @@ hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, c
     g2.Xlpt = w.Xbt + hA;
     g2.ldxlpt = ldp;
     g2.xlpt_bstride = stp;
+    g2.x_round = x_round;
     LpConfig c2{f16, 1, 1, 0, kAllTiles, kRowDesc, kLoZero, kHiM1, kLpEpX21};
     {
       ProfLaunch pl(f16 ? "f16_level_X21" : "bf16_level_X21", full * fh * fh * (fh + 1) + fh * hB * (hB + 1),
@@ -188,8 +189,9 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   const double dn = (double)n;
 
   HIP_TRY(launch_fill_u64(w.status, ~0ull, 1, s));
-  // The residual and correction products read their operands over block-union
-  // K ranges, up to kBand columns past the tiles the splits and epilogues
+  // The residual and correction products read each 256-row panel of their
+  // operands up to the end of the panel's diagonal 256 x 256 block, up to
+  // kBand columns past the 64 x 64 tiles the splits and epilogues
   // write: those bands must hold zeros (nothing writes them afterwards).
   {
     void* planes[6] = {w.PLhi, w.PLlo, w.PX, w.PXthi, w.PXtlo, w.PRt};
@@ -232,13 +234,18 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     for (double v : d) mn = std::min(mn, std::fabs(v));
     if (mn > 0.0) sXf = pow2_scale(1.0 / mn, 11);
   }
+  // The first iterate X0 keeps its FP64 diagonal and takes its low-precision
+  // copies' values (divided by their scale) everywhere below it, so its hi
+  // slice under the same scale holds it exactly and the first residual needs
+  // two products, (hi(N_L) + lo(N_L)) hi(N_X).
+  const int x0_exact = 1;
   {  // leaves in FP64, with row-major and transposed low-precision copies
     const double nl = (double)((n + leaf - 1) / leaf), b = (double)leaf;
     ProfLaunch pl("leaf_f64", nl * b * b * b / 3.0, nl * b * b * (8 + 8 + 4), s);
     HIP_TRY(launch_leaf<double>(n, L, ldl, X, ldx, 0, 1, (int)leaf, o.unit_diag, w.Xb, w.Xbt, f16, ldp, sXf,
-                                w.status, 0, s));
+                                w.status, 0, s, x0_exact));
   }
-  HIP_TRY(lp_levels(n, X, ldx, leaf, f16, w, sL, sXf, s));
+  HIP_TRY(lp_levels(n, X, ldx, leaf, f16, w, sL, sXf, x0_exact, s));
 
   GemmBatch bt{1, 1, n, n, n, n, n, n};
   int iter = 0;
@@ -260,19 +267,22 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   bool px_stale = false;  // the A-role slice (read by the correction only) lags behind X
   for (;;) {
     // residual of the current X
-    double sX = 1.0;
-    if (f16) {
+    // the forward's X0 is exact in its hi slice under the forward's scale:
+    // no lo slice, two products
+    const bool x_hi_exact = x0_exact && iter == 0;
+    double sX = x_hi_exact ? sXf : 1.0;
+    if (f16 && !x_hi_exact) {
       double mx = 0.0;
       HIP_TRY(launch_maxabs<double>(X, n, ldx, 1, 0, w.partial, kPart, w.scal + 6, s));
       HIP_TRY(read_scalar(w.scal + 6, &mx, s));
       sX = pow2_scale(mx, 14);
     }
     if (!x_sliced) {
-      ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + 6), s);
+      ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + (x_hi_exact ? 4 : 6)), s);
       SplitOut so{};
       so.hi_b = w.PX;  // A role of the correction
       so.hi_tb = w.PXthi;  // B role of the residual
-      so.lo_tb = w.PXtlo;
+      so.lo_tb = x_hi_exact ? nullptr : w.PXtlo;
       so.kb = w.kb;
       if (resid_fp64 < 0) {  // the norms of X for the precision decision, from the split's read
         so.sq = w.split_sq;
@@ -330,7 +340,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gr.A_lo = w.PLlo;
     gr.lda = w.kb;
     gr.Bt_hi = w.PXthi;
-    gr.Bt_lo = w.PXtlo;
+    gr.Bt_lo = x_hi_exact ? nullptr : w.PXtlo;
     gr.ldb = w.kb;
     gr.bt = bt;
     gr.alpha = 1.0 / (sL * sX);  // acc = (sL N_L)(sX N_X)
@@ -347,9 +357,12 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     gr.ldrt = w.kb;
     gr.tile_sq = w.tile_sq;
     gr.tile_sqx = w.tile_sqx;
-    LpConfig cr{f16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpResid};
+    const int nsp = x_hi_exact ? 2 : 3;
+    LpConfig cr{f16, nsp, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid};
     {
-      ProfLaunch pl(f16 ? "f16_residual" : "bf16_residual", 3.0 * tri_flops(dn), dn * dn / 2 * (4 * 2 + 8 + 8 + 4 + 2), s);
+      ProfLaunch pl(nsp == 2 ? (f16 ? "f16_residual2" : "bf16_residual2") : (f16 ? "f16_residual" : "bf16_residual"),
+                    nsp * tri_flops(dn),
+                    dn * dn / 2 * ((nsp + 1) * 2 + 8 + 8 + 4 + 2), s);
       HIP_TRY(launch_gemm_lp(gr, cr, s));
     }
     const int64_t ntl = gemm_lp_tiles(bt, kLowerTiles);
@@ -418,7 +431,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       gc.dXn = dx_next;
       gc.kbx = w.kb;
     }
-    LpConfig cc{f16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoBlock, kHiBlock, kLpEpCorr};
+    LpConfig cc{f16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpCorr};
     {
       ProfLaunch pl(f16 ? "f16_correction" : "bf16_correction", tri_flops(dn) + dn * dn,
                     dn * dn / 2 * (2 + 2 + 4 + 16 + (fuse ? 4 : 0)), s);
