@@ -7,8 +7,10 @@
 // v_mfma_f32_32x32x16_{bf16,f16}; each wave owns a 128 x 128 sub-tile
 // (4 x 4 blocks of 32 x 32, 256 FP32 accumulators per lane). Both operands
 // are k-contiguous in memory (B is stored transposed), so a K step is staged
-// by direct global -> LDS 16-byte loads into one of four LDS buffers, issued
-// three stages ahead, and every MFMA operand is one 16-byte LDS read. Lane
+// by direct global -> LDS 16-byte loads into a ring of LDS stages (at most
+// 160 KB: five stages, or three for the 2-product form at K = 32 per stage),
+// issued one stage short of the ring ahead, and every MFMA operand is one
+// 16-byte LDS read. Lane
 // layouts (measured on gfx950): lane l supplies A(l%32, 8(l/32)+e) and
 // B(8(l/32)+e, l%32), e = 0..7, and receives D(8(r/4) + 4(l/32) + r%4, l%32)
 // in register r.
@@ -32,11 +34,13 @@ namespace trinv {
 namespace {
 constexpr int LT = 256;  // workgroup tile (rows and columns)
 
-template <int NSPLIT>
+template <int NSPLIT, int KTW = 0>
 struct LpShape {
-  static constexpr int KT = NSPLIT == 1 ? 32 : 16;  // K per LDS stage
+  static constexpr int KT = KTW ? KTW : (NSPLIT == 1 ? 32 : 16);  // K per LDS stage
   static constexpr int NT = NSPLIT == 1 ? 2 : (NSPLIT == 2 ? 3 : 4);  // staged tiles per stage
-  static constexpr int NBUF = 5;                    // LDS stages (160 KB): loads run NBUF - 1 stages ahead
+  // LDS stages (at most 160 KB): loads run NBUF - 1 stages ahead
+  static constexpr int NBUF = 163840 / (NT * 256 * KT * 2) < 5 ? 163840 / (NT * 256 * KT * 2) : 5;
+  static_assert(NBUF >= 2, "two stages at least");
   static constexpr int CPR = KT / 8;                // 16-byte chunks per tile row
   static constexpr int TILE = LT * KT;              // elements of one staged tile (no padding)
   static constexpr int RPI = 512 / KT;              // tile rows per 1 KB direct-load instruction
@@ -131,9 +135,9 @@ int64_t gemm_lp_tiles(const GemmBatch& bt, int tiles) {
   return bt.nmerge * tm * tn;
 }
 
-template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
+template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI, int KTW>
 __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
-  typedef LpShape<NSPLIT> S;
+  typedef LpShape<NSPLIT, KTW> S;
   constexpr int KT = S::KT;
   // NBUF stages x NT tiles x TILE elements (all of the CU's LDS); after the
   // main loop its first bytes hold the per-wave partial sums of the residual
@@ -320,21 +324,41 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
         }
       }
     } else if constexpr (NSPLIT == 2) {  // B carried exactly by its hi slice: A_lo B_hi + A_hi B_hi
-      u32x4 ah[4], bh[4], al[4];
+      u32x4 ah[2][4], bh[2][4], al[2][4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        al[b] = frag(base, 2, 0, b);
-        bh[b] = frag(base, 1, 0, b);
-        ah[b] = frag(base, 0, 0, b);
+        al[0][b] = frag(base, 2, 0, b);
+        bh[0][b] = frag(base, 1, 0, b);
+        ah[0][b] = frag(base, 0, 0, b);
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int ks = 0; ks < KS; ++ks) {
+        const int c = ks & 1;
+        if (ks + 1 < KS) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(al[i], bh[j], acc[i][j]);
+          for (int b = 0; b < 4; ++b) {
+            al[c ^ 1][b] = frag(base, 2, 16 * (ks + 1), b);
+            bh[c ^ 1][b] = frag(base, 1, 16 * (ks + 1), b);
+            ah[c ^ 1][b] = frag(base, 0, 16 * (ks + 1), b);
+          }
+        }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(ah[i], bh[j], acc[i][j]);
+          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(al[c][i], bh[c][j], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(ah[c][i], bh[c][j], acc[i][j]);
+        if (ks + 1 < KS) {  // 12 reads among 32 MFMAs
+#pragma unroll
+          for (int g = 0; g < 12; ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+          }
+          __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+        }
+      }
     } else {
       u32x4 ah[2][4], bh[2][4], al[2][4], bl[2][4];
 #pragma unroll
@@ -669,11 +693,11 @@ static int64_t lp_grid(const GemmBatch& bt, int tiles) {
   return (nblk + kNumXcd - 1) / kNumXcd * kNumXcd * 16;
 }
 
-template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
+template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI, int KTW = 0>
 static hipError_t go_lp(const LpGemmArgs& a, hipStream_t s, int64_t total) {
-  typedef LpShape<NSPLIT> S;
+  typedef LpShape<NSPLIT, KTW> S;
   const size_t lds = (size_t)S::NBUF * S::NT * S::TILE * sizeof(unsigned short);
-  auto k = k_gemm_lp<F16, NSPLIT, AM, BM, TILES, ORDER, KLO, KHI, EPI>;
+  auto k = k_gemm_lp<F16, NSPLIT, AM, BM, TILES, ORDER, KLO, KHI, EPI, KTW>;
   static bool attr_set = false;  // per instantiation
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -698,10 +722,11 @@ static hipError_t dispatch_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_
   // panel-blocked planes (zero outside their triangles, no masks)
   if (c.amask == 0 && c.bmask == 0 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoN0Pb &&
       c.khi == kHiM1) {
+    // 3 products: K = 16 per stage, five stages; 2 products: K = 32, three stages
     if (c.epi == kLpEpResid && c.nsplit == 3)
       return go_lp<F16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid>(a, s, total);
     if (c.epi == kLpEpResid && c.nsplit == 2)
-      return go_lp<F16, 2, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid>(a, s, total);
+      return go_lp<F16, 2, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid, 32>(a, s, total);
     if (c.epi == kLpEpResid && c.nsplit == 1)
       return go_lp<F16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid>(a, s, total);
     if (c.epi == kLpEpCorr && c.nsplit == 1)
