@@ -315,13 +315,6 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(fa[c][i], fb[c][j], acc[i][j]);
-        if (ks + 1 < KS) {  // interleave the next k step's 8 reads with these 16 MFMAs
-#pragma unroll
-          for (int g = 0; g < 8; ++g) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // MFMA
-          }
-        }
       }
     } else if constexpr (NSPLIT == 2) {  // B carried exactly by its hi slice: A_lo B_hi + A_hi B_hi
       u32x4 ah[2][4], bh[2][4], al[2][4];
@@ -350,14 +343,6 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(ah[c][i], bh[c][j], acc[i][j]);
-        if (ks + 1 < KS) {  // 12 reads among 32 MFMAs
-#pragma unroll
-          for (int g = 0; g < 12; ++g) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-          }
-          __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
-        }
       }
     } else {
       u32x4 ah[2][4], bh[2][4], al[2][4], bl[2][4];
@@ -393,15 +378,25 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(ah[c][i], bh[c][j], acc[i][j]);
-        if (ks + 1 < KS) {  // 16 reads among 48 MFMAs
-#pragma unroll
-          for (int g = 0; g < 16; ++g) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
-          }
-        }
       }
     }
+    // Instruction order of the whole stage (LDS reads return in order, so the
+    // waits before the MFMAs count down as the fragments arrive): the first k
+    // step's RD reads, then each k step's MF MFMAs with the next k step's RD
+    // reads spread among them.
+    constexpr int RD = 4 * (NSPLIT + 1), MF = 16 * NSPLIT;
+    constexpr int Q = MF / RD, REM = MF - Q * RD;
+    __builtin_amdgcn_sched_group_barrier(0x100, RD, 0);  // DS reads
+#pragma unroll
+    for (int ks = 0; ks + 1 < KS; ++ks) {
+#pragma unroll
+      for (int g = 0; g < RD; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, Q, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      if (REM) __builtin_amdgcn_sched_group_barrier(0x008, REM, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, MF, 0);
   };
 
   // NBUF-stage pipeline: stage st lives in buffer st % NBUF; its loads were
