@@ -346,13 +346,15 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
       }
     } else {
       u32x4 ah[2][4], bh[2][4], al[2][4], bl[2][4];
+      // the first product's fragments first
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        ah[0][b] = frag(base, 0, 0, b);
-        bl[0][b] = frag(base, 3, 0, b);
-        al[0][b] = frag(base, 2, 0, b);
-        bh[0][b] = frag(base, 1, 0, b);
-      }
+      for (int b = 0; b < 4; ++b) ah[0][b] = frag(base, 0, 0, b);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bl[0][b] = frag(base, 3, 0, b);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) al[0][b] = frag(base, 2, 0, b);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bh[0][b] = frag(base, 1, 0, b);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const int c = ks & 1;
@@ -386,6 +388,18 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
     // reads spread among them.
     constexpr int RD = 4 * (NSPLIT + 1), MF = 16 * NSPLIT;
     constexpr int Q = MF / RD, REM = MF - Q * RD;
+    if constexpr (NSPLIT == 3 && KS == 1) {
+      // one k step: the first product's 8 reads, its 16 MFMAs with the other
+      // 8 reads among them, then the other two products
+      __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 32, 0);
+      return;
+    }
     __builtin_amdgcn_sched_group_barrier(0x100, RD, 0);  // DS reads
 #pragma unroll
     for (int ks = 0; ks + 1 < KS; ++ks) {
