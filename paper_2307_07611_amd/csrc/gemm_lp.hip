@@ -33,6 +33,7 @@ namespace trinv {
 
 namespace {
 constexpr int LT = 256;  // workgroup tile (rows and columns)
+constexpr int kTrLd = LT + 8;  // row length of a transposed tile staged in LDS (16-byte rows, fewer bank conflicts)
 
 template <int NSPLIT, int KTW = 0>
 struct LpShape {
@@ -53,6 +54,7 @@ struct LpShape {
 };
 
 typedef unsigned short u16;
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int F16>
@@ -469,17 +471,10 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
           u16 o[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) o[e] = to_lp<F16>((float)(alpha * (double)blk[4 * q + e]));
-          u16* dst = (u16*)a.Ot + z * a.ot_bstride + col * a.ldot + row0;
-          if (full || (colok && row0 + 3 < M)) {
-            uint2 v;
-            v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
-            v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
-            *(uint2*)dst = v;
-          } else if (colok) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (row0 + e < M) dst[e] = o[e];
-          }
+          uint2 v;
+          v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
+          v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
+          *(uint2*)(lds + (col - n0) * kTrLd + (row0 - m0)) = v;  // transposed tile, stored below
         } else if (EPI == kLpEpX21) {
           u16 o[4];
 #pragma unroll
@@ -492,17 +487,10 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
               ((u16*)a.Xlp)[z * a.xlp_bstride + row * a.ldxlp + col] = o[e];
             }
           }
-          u16* dst = (u16*)a.Xlpt + z * a.xlpt_bstride + col * a.ldxlpt + row0;
-          if (full || (colok && row0 + 3 < M)) {
-            uint2 v;
-            v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
-            v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
-            *(uint2*)dst = v;
-          } else if (colok) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (row0 + e < M) dst[e] = o[e];
-          }
+          uint2 v;
+          v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
+          v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
+          *(uint2*)(lds + (col - n0) * kTrLd + (row0 - m0)) = v;  // transposed tile, stored below
         }
       }
       if constexpr (EPI == kLpEpResid || EPI == kLpEpCorr) {
@@ -668,11 +656,39 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
       }
     });
 
+  if constexpr (EPI == kLpEpT || EPI == kLpEpX21) {
+    // The tile's transposed low-precision output, staged in LDS (row r of it
+    // is column n0 + r of the product), leaves in 16-byte pieces of its rows.
+    __syncthreads();
+    u16* const Tb = EPI == kLpEpT ? (u16*)a.Ot + z * a.ot_bstride : (u16*)a.Xlpt + z * a.xlpt_bstride;
+    const int64_t ldt = EPI == kLpEpT ? a.ldot : a.ldxlpt;
+    const bool al16 = ((((uintptr_t)Tb) | (uintptr_t)(ldt * 2)) & 15) == 0;
+    for (int c = tid; c < LT * (LT / 8); c += 256) {
+      const int r = c / (LT / 8), p = (c % (LT / 8)) * 8;
+      if (n0 + r >= N) continue;
+      u16* d = Tb + (n0 + r) * ldt + m0 + p;
+      const u16* sp = lds + r * kTrLd + p;
+      if (al16 && m0 + p + 8 <= M) {
+        *(u32x4*)d = *(const u32x4*)sp;
+      } else {
+        for (int e = 0; e < 8; ++e)
+          if (m0 + p + e < M) d[e] = sp[e];
+      }
+    }
+  }
   if (EPI == kLpEpX21) {  // zero the FP64 X12 block: rows n0.., cols m0.. (transposed tile)
     double* Zb = a.Xmirror + z * a.x_bstride;
-    for (int e = tid; e < LT * LT; e += 256) {
+    const bool al16 = ((((uintptr_t)Zb) | (uintptr_t)(a.ldx * 8)) & 15) == 0 && (m0 & 1) == 0;
+    for (int e = 2 * tid; e < LT * LT; e += 512) {
       const int64_t mr = n0 + e / LT, mc = m0 + e % LT;
-      if (mr < N && mc < M) Zb[mr * a.ldx + mc] = 0.0;
+      if (mr >= N) continue;
+      double* d = Zb + mr * a.ldx + mc;
+      if (al16 && mc + 2 <= M) {
+        __builtin_nontemporal_store((f64x2){0.0, 0.0}, (f64x2*)d);
+      } else {
+        if (mc < M) d[0] = 0.0;
+        if (mc + 1 < M) d[1] = 0.0;
+      }
     }
   }
   if (EPI == kLpEpResid) {
