@@ -22,18 +22,18 @@ constexpr int kNumXcd = 8;
 // Maps a dispatch index to a logical tile index so that each XCD works on
 // runs of `chunk` consecutive logical tiles (which share operand panels in
 // that XCD's L2) while the runs rotate over the XCDs in logical order (so a
-// heavy-first logical order stays heavy-first on every XCD); successive
-// rounds of eight runs alternate direction over the XCDs, so that no XCD
-// takes the heaviest run of every round. Valid for any total; indices past
-// the last full round map to themselves.
+// heavy-first logical order stays heavy-first on every XCD). XCD x takes runs
+// x, x + 8, x + 16, ...: in the column-ordered tile lists of the level
+// products these cover the same tile rows of successive columns, so their A
+// panels stay in that XCD's L2. Valid for any total; indices past the last
+// full round map to themselves.
 __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t total, int chunk) {
   const int64_t round = (int64_t)kNumXcd * chunk;
   const int64_t full = (total / round) * round;
   if (w >= full) return w;
   const int64_t xcd = w % kNumXcd;
   const int64_t q = w / kNumXcd;
-  const int64_t r = q / chunk;
-  return r * round + ((r & 1) ? kNumXcd - 1 - xcd : xcd) * chunk + (q % chunk);
+  return (q / chunk) * round + xcd * chunk + (q % chunk);
 }
 
 __device__ __forceinline__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }

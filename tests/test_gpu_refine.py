@@ -84,6 +84,43 @@ def test_bf16_not_converged_reports_forward_residual(trinv):
     assert e.value.info["iterations"] == 0
 
 
+def _bf16_exact(v):
+    f = v.astype(np.float32)
+    return (f.astype(np.float64) == v) & ((f.view(np.uint32) & 0xFFFF) == 0)
+
+
+@pytest.mark.parametrize("mode", ["bf16_refine", "f16_refine"])
+@pytest.mark.parametrize("n,leaf", [(640, 64), (1000, 128)])
+def test_first_iterate_exact_in_low_precision(trinv, mode, n, leaf):
+    """The first iterate keeps the FP64 diagonal 1 / L_ii (bitwise) and holds,
+    below it, values of the low-precision type times one power-of-two scale
+    (1 for BF16; for FP16 2^(11 - e) with 1 / min |L_ii| < 2^e), so the first
+    residual's two-product form is exact in X. max_iter = 0 returns it."""
+    import torch
+    from paper_2307_07611_amd import _lib
+
+    banner(f"{mode} first iterate n={n} leaf={leaf}")
+    L = synth.lower_triangular(n, 12)
+    X = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.TrinvError) as e:
+        trinv.tril_inverse(dev(L), mode, leaf=leaf, max_iter=0, out=X)
+    assert e.value.code == _lib.ERR_NOT_CONVERGED
+    Xh = host(X)
+    d = np.diag(L)
+    np.testing.assert_array_equal(np.diag(Xh), 1.0 / d)
+    off = Xh[np.tril_indices(n, -1)]
+    if mode == "bf16_refine":
+        assert np.all(_bf16_exact(off))
+    else:
+        ex = np.frexp(np.max(1.0 / np.abs(d)))[1]  # 1 / min |L_ii| < 2^ex
+        scaled = off * 2.0 ** (11 - ex)
+        assert np.all(scaled.astype(np.float16).astype(np.float64) == scaled)
+    np.testing.assert_array_equal(np.triu(Xh, 1), 0.0)
+    # it is the low-precision forward: close to the oracle, not equal
+    Xo = oracle.tril_inverse(L)
+    assert 0.0 < rel_fro(Xh, Xo) < 1e-2
+
+
 @pytest.mark.parametrize("mode", ["bf16_refine", "f16_refine"])
 def test_singular(trinv, mode):
     from paper_2307_07611_amd import _lib
