@@ -37,7 +37,7 @@ constexpr int kTrLd = LT + 8;  // row length of a transposed tile staged in LDS 
 
 template <int NSPLIT, int KTW = 0>
 struct LpShape {
-  static constexpr int KT = KTW ? KTW : (NSPLIT == 1 ? 32 : 16);  // K per LDS stage
+  static constexpr int KT = KTW ? KTW : (NSPLIT == 3 ? 16 : 32);  // K per LDS stage
   static constexpr int NT = NSPLIT == 1 ? 2 : (NSPLIT == 2 ? 3 : 4);  // staged tiles per stage
   // LDS stages (at most 160 KB): loads run NBUF - 1 stages ahead
   static constexpr int NBUF = 163840 / (NT * 256 * KT * 2) < 5 ? 163840 / (NT * 256 * KT * 2) : 5;
@@ -294,155 +294,119 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  auto stage_compute = [&](const u16* base) {
-    constexpr int KS = S::KT / 16;
-    if (NSPLIT == 1) {
-      u32x4 fa[2][4], fb[2][4];
+  // Fragments of one stage: fr[ks][tile][block]. Products of a k step
+  // (A tile x B tile): A_hi B_hi (1); A_lo B_hi, A_hi B_hi (2);
+  // A_hi B_lo, A_lo B_hi, A_hi B_hi (3).
+  constexpr int KS = S::KT / 16, NT = S::NT;
+  static_assert(KS == 2 || NSPLIT == 3, "two k steps per stage, or the 3-product stage at K = 16");
+  u32x4 fr[KS][NT][4];
+  auto prod_a = [](int p) constexpr { return NSPLIT == 1 ? 0 : (NSPLIT == 2 ? (p == 0 ? 2 : 0) : (p == 1 ? 2 : 0)); };
+  auto prod_b = [](int p) constexpr { return NSPLIT == 3 ? (p == 0 ? 3 : 1) : 1; };
+  auto read_tile = [&](const u16* base, auto KSI, auto TTI) __attribute__((always_inline)) {
+    constexpr int ks = decltype(KSI)::value, tt = decltype(TTI)::value;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        fa[0][b] = frag(base, 0, 0, b);
-        fb[0][b] = frag(base, 1, 0, b);
-      }
+    for (int b = 0; b < 4; ++b) fr[ks][tt][b] = frag(base, tt, 16 * ks, b);
+  };
+  auto mma_prod = [&](auto KSI, auto PI) __attribute__((always_inline)) {
+    constexpr int ks = decltype(KSI)::value, p = decltype(PI)::value;
+    constexpr int ta = prod_a(p), tb_ = prod_b(p);
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int c = ks & 1;
-        if (ks + 1 < KS) {
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            fa[c ^ 1][b] = frag(base, 0, 16 * (ks + 1), b);
-            fb[c ^ 1][b] = frag(base, 1, 16 * (ks + 1), b);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(fa[c][i], fb[c][j], acc[i][j]);
-      }
-    } else if constexpr (NSPLIT == 2) {  // B carried exactly by its hi slice: A_lo B_hi + A_hi B_hi
-      u32x4 ah[2][4], bh[2][4], al[2][4];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        al[0][b] = frag(base, 2, 0, b);
-        bh[0][b] = frag(base, 1, 0, b);
-        ah[0][b] = frag(base, 0, 0, b);
-      }
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int c = ks & 1;
-        if (ks + 1 < KS) {
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            al[c ^ 1][b] = frag(base, 2, 16 * (ks + 1), b);
-            bh[c ^ 1][b] = frag(base, 1, 16 * (ks + 1), b);
-            ah[c ^ 1][b] = frag(base, 0, 16 * (ks + 1), b);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(al[c][i], bh[c][j], acc[i][j]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(ah[c][i], bh[c][j], acc[i][j]);
-      }
+      for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(fr[ks][ta][i], fr[ks][tb_][j], acc[i][j]);
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  // A stage is split around the barrier that makes the next stage readable:
+  // its "head" fragments (k step 0; for the 3-product stage A_hi and B_lo)
+  // are read before the stage starts, the rest while the head products run;
+  // after the barrier the next stage's head fragments are read while this
+  // stage's "tail" products (which use only the rest) run.
+  auto head_reads = [&](const u16* base) __attribute__((always_inline)) {
+    if constexpr (KS == 2) {
+      static_for<0, NT>([&](auto T) { read_tile(base, I0{}, T); });
     } else {
-      u32x4 ah[2][4], bh[2][4], al[2][4], bl[2][4];
-      // the first product's fragments first
-#pragma unroll
-      for (int b = 0; b < 4; ++b) ah[0][b] = frag(base, 0, 0, b);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bl[0][b] = frag(base, 3, 0, b);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) al[0][b] = frag(base, 2, 0, b);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bh[0][b] = frag(base, 1, 0, b);
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int c = ks & 1;
-        if (ks + 1 < KS) {
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            ah[c ^ 1][b] = frag(base, 0, 16 * (ks + 1), b);
-            bl[c ^ 1][b] = frag(base, 3, 16 * (ks + 1), b);
-            al[c ^ 1][b] = frag(base, 2, 16 * (ks + 1), b);
-            bh[c ^ 1][b] = frag(base, 1, 16 * (ks + 1), b);
-          }
-        }
-        // dependent updates of one accumulator are 16 MFMAs apart
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(ah[c][i], bl[c][j], acc[i][j]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(al[c][i], bh[c][j], acc[i][j]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(ah[c][i], bh[c][j], acc[i][j]);
-      }
+      read_tile(base, I0{}, I0{});
+      read_tile(base, I0{}, I3{});
     }
-    // Instruction order of the whole stage (LDS reads return in order, so the
-    // waits before the MFMAs count down as the fragments arrive): the first k
-    // step's RD reads, then each k step's MF MFMAs with the next k step's RD
-    // reads spread among them.
-    constexpr int RD = 4 * (NSPLIT + 1), MF = 16 * NSPLIT;
-    constexpr int Q = MF / RD, REM = MF - Q * RD;
-    if constexpr (NSPLIT == 3 && KS == 1) {
-      // one k step: the first product's 8 reads, its 16 MFMAs with the other
-      // 8 reads among them, then the other two products
-      __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+  };
+  auto rest_and_head_products = [&](const u16* base) __attribute__((always_inline)) {
+    if constexpr (KS == 2) {
+      static_for<0, NT>([&](auto T) { read_tile(base, I1{}, T); });
+      static_for<0, NSPLIT>([&](auto P) { mma_prod(I0{}, P); });
+      constexpr int RD = 4 * NT, MF = 16 * NSPLIT, Q = MF / RD, REM = MF - Q * RD;
+#pragma unroll
+      for (int g = 0; g < RD; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, Q, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+      }
+      if (REM) __builtin_amdgcn_sched_group_barrier(0x008, REM, 0);
+    } else {
+      read_tile(base, I0{}, I2{});
+      read_tile(base, I0{}, I1{});
+      mma_prod(I0{}, I0{});  // A_hi B_lo (head)
+      mma_prod(I0{}, I2{});  // A_hi B_hi (needs B_hi)
 #pragma unroll
       for (int g = 0; g < 8; ++g) {
         __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
       }
-      __builtin_amdgcn_sched_group_barrier(0x008, 32, 0);
-      return;
+      __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x100, RD, 0);  // DS reads
-#pragma unroll
-    for (int ks = 0; ks + 1 < KS; ++ks) {
-#pragma unroll
-      for (int g = 0; g < RD; ++g) {
-        __builtin_amdgcn_sched_group_barrier(0x008, Q, 0);  // MFMA
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-      }
-      if (REM) __builtin_amdgcn_sched_group_barrier(0x008, REM, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(0x008, MF, 0);
+  };
+  auto tail_products = [&]() __attribute__((always_inline)) {
+    if constexpr (KS == 2)
+      static_for<0, NSPLIT>([&](auto P) { mma_prod(I1{}, P); });
+    else
+      mma_prod(I0{}, I1{});  // A_lo B_hi
   };
 
-  // NBUF-stage pipeline: stage st lives in buffer st % NBUF; its loads were
-  // issued NBUF - 1 stages earlier. Before computing it, each wave waits until
-  // only its loads of the newer stages are outstanding, then the barrier makes
-  // every wave's part visible and frees the buffer of stage st - 1 for stage
-  // st + NBUF - 1.
+  // NBUF-stage pipeline: stage st lives in buffer st % NBUF. The loads of
+  // stages 0 .. NBUF - 1 are issued up front; stage st + NBUF is issued into
+  // the buffer of stage st once every wave has read stage st (the barrier
+  // that makes stage st + 1 readable). Before that barrier each wave waits
+  // until only its loads of the newer stages are outstanding.
   constexpr int NBUF = S::NBUF;
   constexpr int LPS = S::NT * S::IPW;  // direct loads per thread and stage
   if (klo < khi) {
     const int nst = (int)((khi - klo + S::KT - 1) / S::KT);
-#pragma unroll
-    for (int p = 0; p < NBUF - 1; ++p)
-      if (p < nst) issue(p, (int64_t)p * S::KT);
-    for (int st = 0; st < nst; ++st) {
-      const int buf = st % NBUF;
+    auto ready = [&](int st) __attribute__((always_inline)) {
       if (st + NBUF - 2 < nst)
         wait_barrier<(NBUF - 2) * LPS>();
       else
         wait_barrier<0>();
-      if (st + NBUF - 1 < nst) issue((st + NBUF - 1) % NBUF, (int64_t)(st + NBUF - 1) * S::KT);
+    };
+    auto guard_mask = [&](int st) __attribute__((always_inline)) {
       const int64_t k0 = klo + (int64_t)st * S::KT;
       bool guard = (k0 + S::KT > K);
       if (AM != 0 && k0 + S::KT > m0 && k0 < m0 + LT) guard = true;
       if (BM != 0 && k0 + S::KT > n0 && k0 < n0 + LT) guard = true;
       if (guard) {
-        mask_lds(buf, k0);
+        mask_lds(st % NBUF, k0);
         wait_barrier<LPS * (NBUF - 1)>();  // LDS writes of the mask visible (loads stay in flight)
       }
-      stage_compute(lds + buf * (S::NT * S::TILE));
+    };
+    auto stage_base = [&](int st) { return lds + (st % NBUF) * (NT * S::TILE); };
+#pragma unroll
+    for (int p = 0; p < NBUF - 1; ++p)
+      if (p < nst) issue(p, (int64_t)p * S::KT);
+    ready(0);
+    if (NBUF - 1 < nst) issue(NBUF - 1, (int64_t)(NBUF - 1) * S::KT);
+    guard_mask(0);
+    head_reads(stage_base(0));
+    for (int st = 0; st < nst; ++st) {
+      rest_and_head_products(stage_base(st));
+      __builtin_amdgcn_sched_barrier(0);
+      if (st + 1 < nst) {
+        ready(st + 1);  // also: every wave has read stage st
+        if (st + NBUF < nst) issue(st % NBUF, (int64_t)(st + NBUF) * S::KT);
+        guard_mask(st + 1);
+        head_reads(stage_base(st + 1));
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      tail_products();
     }
     wait_barrier<0>();
   }
