@@ -69,10 +69,13 @@ typedef enum {
    * ||L X - I||_F / (||L||_F ||X||_F) <= opts->tol. The residual is
    * assembled, stored and reduced in FP64; its O(n^3) strictly-lower product
    * runs on split BF16 slices, so the whole residual stays accurate to far
-   * below the tolerance. */
+   * below the tolerance. The first iterate keeps the FP64 diagonal 1 / L_ii
+   * and holds BF16 values below it (the values its products read); with
+   * max_iter = 0 that iterate is what X holds on return. */
   TRINV_BF16_REFINE = 2,
   /* As TRINV_BF16_REFINE with FP16 slices (power-of-two scaled rows and
-   * columns to keep them in FP16 range). */
+   * columns to keep them in FP16 range); the first iterate holds FP16 values
+   * times one power-of-two scale below its diagonal. */
   TRINV_F16_REFINE = 3
 } trinv_mode;
 
