@@ -175,6 +175,41 @@ int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t *n_host, c
                                void *X_packed, int32_t *status_dev, const trinv_opts *opts, void *ws,
                                size_t ws_bytes, trinv_stream_t stream);
 
+/* A configuration of the persistent batched launch. */
+typedef struct {
+  int32_t wg_tile_from; /* block order from which the level products use 128 x 128
+                           workgroup tiles (smaller blocks: 32 x 32 wave tiles);
+                           1024 = never. 0 = not applicable (level path). */
+  int32_t wgs_per_cu;   /* resident workgroups per CU (0 = not applicable) */
+  float ms;             /* time of one launch pair with it; -1 if not timed */
+} trinv_batched_config;
+
+/*
+ * Autotuner of trinv_tril_inverse_batched (not in the paper): times the
+ * persistent launch with every candidate configuration (wg_tile_from in
+ * {128, 256, 1024}; wgs_per_cu from 1 up to the occupancy limit in powers of
+ * two, and that limit) on the caller's buffers and stream, one untimed launch
+ * and the fastest of three each, and keeps the fastest for this batch's order
+ * signature (mode, count, sum of n_i, sum of n_i^2, largest n_i) for the rest
+ * of the process: later trinv_tril_inverse_batched calls with the same
+ * signature use it (the default is 128 and the occupancy limit). Arguments and
+ * errors as trinv_tril_inverse_batched. On return X_packed and status_dev hold
+ * the result of the chosen configuration; `out` (nullable) receives it.
+ * Uniform batches that take the level path have nothing to tune (out->ms =
+ * -1). Synchronises `stream` (not for graph capture: tune first, then
+ * capture).
+ */
+int trinv_batched_autotune(int mode, int64_t batch, const int32_t *n_host, const int32_t *n_dev,
+                           const int64_t *off_host, const int64_t *off_dev, const void *L_packed,
+                           void *X_packed, int32_t *status_dev, const trinv_opts *opts, void *ws,
+                           size_t ws_bytes, trinv_stream_t stream, trinv_batched_config *out);
+
+/* Sets the configuration later trinv_tril_inverse_batched calls use for
+ * batches with this order signature (as trinv_batched_autotune would), e.g.
+ * one an earlier process found. cfg->wg_tile_from >= 128, cfg->wgs_per_cu >= 0
+ * (0 or above the occupancy limit: that limit); else TRINV_ERR_ARG. */
+int trinv_batched_set_config(int mode, int64_t batch, const int32_t *n_host, const trinv_batched_config *cfg);
+
 /*
  * Adjoint of X = L^-1 for a strided batch of lower-triangular matrices:
  *     gradL = -tril(X^T G X^T)

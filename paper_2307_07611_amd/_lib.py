@@ -19,7 +19,9 @@ OK, ERR_ARG, ERR_SINGULAR, ERR_NONFINITE, ERR_NOT_CONVERGED, ERR_HIP, ERR_UNSUPP
 
 EXPORTS = [
     "trinv_default_opts", "trinv_status_string", "trinv_workspace_bytes", "trinv_tril_inverse",
-    "trinv_batched_workspace_bytes", "trinv_tril_inverse_batched", "trinv_backward_workspace_bytes",
+    "trinv_batched_workspace_bytes", "trinv_tril_inverse_batched", "trinv_batched_autotune",
+    "trinv_batched_set_config",
+    "trinv_backward_workspace_bytes",
     "trinv_tril_inverse_backward", "trinv_factored_workspace_bytes", "trinv_factored_inverse",
     "trinv_residual_workspace_bytes", "trinv_residual", "trinv_profile_enable", "trinv_profile_read",
     "trinv_skul_workspace_bytes", "trinv_skul", "trinv_sqr_workspace_bytes", "trinv_sqr",
@@ -36,6 +38,10 @@ class Opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int32), ("unit_diag", ctypes.c_int32), ("upper", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("blocking", ctypes.c_int32),
                 ("check", ctypes.c_int32), ("beta", ctypes.c_int32)]
+
+
+class BatchedConfig(ctypes.Structure):
+    _fields_ = [("wg_tile_from", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 class Info(ctypes.Structure):
@@ -73,6 +79,10 @@ def load():
     lib.trinv_tril_inverse_batched.argtypes = [ctypes.c_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                                ctypes.POINTER(Opts), _vp, _sz, _vp]
     lib.trinv_tril_inverse_batched.restype = ctypes.c_int
+    lib.trinv_batched_autotune.argtypes = lib.trinv_tril_inverse_batched.argtypes + [ctypes.POINTER(BatchedConfig)]
+    lib.trinv_batched_autotune.restype = ctypes.c_int
+    lib.trinv_batched_set_config.argtypes = [ctypes.c_int, _i64, _vp, ctypes.POINTER(BatchedConfig)]
+    lib.trinv_batched_set_config.restype = ctypes.c_int
     lib.trinv_backward_workspace_bytes.argtypes = [ctypes.c_int, _i64, _i64]
     lib.trinv_backward_workspace_bytes.restype = _sz
     lib.trinv_tril_inverse_backward.argtypes = [ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _sz, _vp]

@@ -177,6 +177,57 @@ def tril_inverse_batched(L_packed: torch.Tensor, sizes, offsets=None, mode=None,
     return X, status
 
 
+def batched_autotune(L_packed: torch.Tensor, sizes, offsets=None, mode=None, *, leaf=0, out=None, workspace=None,
+                     n_dev=None, off_dev=None, status=None) -> dict:
+    """Times the persistent batched launch's configurations on this batch and
+    keeps the fastest for batches with the same orders (trinv_batched_autotune);
+    returns it as a dict (wg_tile_from, wgs_per_cu, ms). X (``out``) and
+    ``status`` hold the result of the chosen configuration."""
+    _check_dev(L_packed)
+    import numpy as np
+
+    sizes_np = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
+    if offsets is None:
+        offsets = np.zeros(len(sizes_np), dtype=np.int64)
+        if len(sizes_np) > 1:
+            offsets[1:] = np.cumsum(sizes_np[:-1].astype(np.int64) ** 2)
+    off_np = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    m = _mode_for(L_packed, mode)
+    batch = len(sizes_np)
+    dev = L_packed.device
+    if n_dev is None:
+        n_dev = torch.from_numpy(sizes_np).to(dev)
+    if off_dev is None:
+        off_dev = torch.from_numpy(off_np).to(dev)
+    X = out if out is not None else torch.empty_like(L_packed)
+    if status is None:
+        status = torch.empty(batch, dtype=torch.int32, device=dev)
+    lib = _lib.load()
+    o = _opts(leaf=leaf, blocking=False)
+    nbytes = lib.trinv_batched_workspace_bytes(m, batch, sizes_np.ctypes.data, ctypes.byref(o))
+    ws = workspace if workspace is not None else _workspace(nbytes, dev)
+    cfg = _lib.BatchedConfig()
+    st = lib.trinv_batched_autotune(m, batch, sizes_np.ctypes.data, n_dev.data_ptr(), off_np.ctypes.data,
+                                    off_dev.data_ptr(), L_packed.data_ptr(), X.data_ptr(), status.data_ptr(),
+                                    ctypes.byref(o), ws.data_ptr(), ws.numel(), _stream(), ctypes.byref(cfg))
+    if st != _lib.OK:
+        raise _lib.TrinvError(st, "trinv_batched_autotune")
+    return {"wg_tile_from": cfg.wg_tile_from, "wgs_per_cu": cfg.wgs_per_cu, "ms": cfg.ms}
+
+
+def batched_set_config(sizes, mode, wg_tile_from, wgs_per_cu=0):
+    """Pin the persistent batched launch's configuration for batches with these
+    orders (trinv_batched_set_config)."""
+    import numpy as np
+
+    sizes_np = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
+    cfg = _lib.BatchedConfig(wg_tile_from, wgs_per_cu, -1.0)
+    st = _lib.load().trinv_batched_set_config(_lib.MODES[mode], len(sizes_np), sizes_np.ctypes.data,
+                                              ctypes.byref(cfg))
+    if st != _lib.OK:
+        raise _lib.TrinvError(st, "trinv_batched_set_config")
+
+
 def skul(A: torch.Tensor, *, want_ainv=True, leaf=0, blocking=True):
     """Algorithm SKUL: (L, U, S, K, Ainv) with A = L U (Crout, U unit upper, no
     pivoting), S = U^-1, K = L^-1 and Ainv = S K (None if not wanted)."""
@@ -270,6 +321,7 @@ class BatchedGraph:
                                                    ctypes.byref(o))
         self.ws = _workspace(nbytes, self.L.device)
         self.graph = None
+        self.config = None
 
     def _call(self):
         tril_inverse_batched(self.L, self.sizes, self.offsets, self.mode_name, blocking=False, leaf=self.leaf,
@@ -279,7 +331,17 @@ class BatchedGraph:
     def run_eager(self):
         self._call()
 
-    def capture(self):
+    def tune(self):
+        """Run the autotuner on this batch layout (the current contents of
+        ``self.L``); the chosen configuration is used by every later launch,
+        captured ones included."""
+        self.config = batched_autotune(self.L, self.sizes, self.offsets, self.mode_name, leaf=self.leaf, out=self.X,
+                                       workspace=self.ws, n_dev=self.n_dev, off_dev=self.off_dev, status=self.status)
+        return self.config
+
+    def capture(self, tune=True):
+        if tune:
+            self.tune()  # outside the graph: it times launches and synchronises
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):

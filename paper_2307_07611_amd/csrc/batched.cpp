@@ -5,6 +5,9 @@
 // compute units instead runs the level recursion with the batch as an extra
 // launch dimension (every level product spread over the whole chip).
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "api_internal.h"
@@ -51,6 +54,69 @@ WsLevels carve_levels(Carve& c, int mode, int64_t batch, int64_t n, int64_t leaf
 
 int64_t level_leaf(int mode, int64_t n, int32_t opt_leaf) { return opt_leaf ? opt_leaf : default_leaf(mode, n); }
 
+// Tunable parameters of the persistent launch: the block order from which
+// level products use 128 x 128 workgroup tiles (below it: 32 x 32 wave
+// tiles; 1024 never for orders <= 1024) and the resident workgroups per CU
+// (0: the occupancy limit).
+struct PersistentConfig {
+  int wg_from = 128;
+  int per_cu = 0;
+};
+
+// The kernel's work depends on the orders only: a batch is keyed by its mode,
+// count, sum of orders, sum of squared orders and largest order.
+typedef std::tuple<int, int64_t, int64_t, int64_t, int> BatchKey;
+
+std::mutex g_tuned_mu;
+std::map<BatchKey, PersistentConfig> g_tuned;  // autotuner results, per process
+
+PersistentConfig tuned_config(const BatchKey& k) {
+  std::lock_guard<std::mutex> lock(g_tuned_mu);
+  auto it = g_tuned.find(k);
+  return it == g_tuned.end() ? PersistentConfig{} : it->second;
+}
+
+// Validates the batch (as trinv_tril_inverse_batched documents) and fills
+// its key and algorithmic work; TRINV_OK or the error status.
+int check_batch(int mode, int64_t batch, const int32_t* n_host, const int32_t* n_dev, const int64_t* off_host,
+                const int64_t* off_dev, const void* L_packed, void* X_packed, int32_t* status_dev,
+                const trinv_opts& o, BatchKey* key, double* flops, double* bytes) {
+  if (batch < 0 || batch > INT32_MAX) return TRINV_ERR_ARG;
+  if (!n_host || !off_host || !n_dev || !off_dev || !L_packed || !X_packed || !status_dev) return TRINV_ERR_ARG;
+  if (mode != TRINV_F64 && mode != TRINV_F32) return TRINV_ERR_UNSUPPORTED;
+  if (o.upper) return TRINV_ERR_UNSUPPORTED;
+  if (o.leaf != 0 && o.leaf != 16) return TRINV_ERR_ARG;
+  const size_t es = mode == TRINV_F32 ? 4 : 8;
+  int64_t extent = 0, s1 = 0, s2 = 0;
+  int nmax = 0;
+  *flops = 0.0;
+  *bytes = 0.0;
+  for (int64_t i = 0; i < batch; ++i) {
+    const int64_t n = n_host[i];
+    if (n < 1 || n > 1024 || off_host[i] < 0) return TRINV_ERR_ARG;
+    extent = std::max<int64_t>(extent, off_host[i] + n * n);
+    *flops += (double)n * n * n / 3.0;
+    *bytes += es * ((double)n * (n + 1) / 2 + (double)n * n);  // lower triangle in, full X out
+    s1 += n;
+    s2 += n * n;
+    nmax = std::max<int>(nmax, (int)n);
+  }
+  if (overlaps(L_packed, (size_t)extent * es, X_packed, (size_t)extent * es)) return TRINV_ERR_ARG;
+  *key = BatchKey(mode, batch, s1, s2, nmax);
+  return TRINV_OK;
+}
+
+// The persistent launch pair with configuration c.
+hipError_t launch_persistent(int mode, int64_t batch, const int32_t* n_dev, const int64_t* off_dev,
+                             const void* L_packed, void* X_packed, int32_t* status_dev, const WsPersistent& w,
+                             int unit, const PersistentConfig& c, hipStream_t s) {
+  if (mode == TRINV_F32)
+    return launch_batched<float>(batch, n_dev, off_dev, (const float*)L_packed, (float*)X_packed, status_dev,
+                                 w.order, w.queue, unit, batched_grid<float>(batch, c.per_cu), c.wg_from, s);
+  return launch_batched<double>(batch, n_dev, off_dev, (const double*)L_packed, (double*)X_packed, status_dev,
+                                w.order, w.queue, unit, batched_grid<double>(batch, c.per_cu), c.wg_from, s);
+}
+
 }  // namespace
 
 extern "C" size_t trinv_batched_workspace_bytes(int mode, int64_t batch, const int32_t* n_host,
@@ -74,22 +140,12 @@ extern "C" int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t
                                           size_t ws_bytes, trinv_stream_t stream) {
   if (batch < 0 || batch > INT32_MAX) return TRINV_ERR_ARG;
   if (batch == 0) return TRINV_OK;
-  if (!n_host || !off_host || !n_dev || !off_dev || !L_packed || !X_packed || !status_dev) return TRINV_ERR_ARG;
-  if (mode != TRINV_F64 && mode != TRINV_F32) return TRINV_ERR_UNSUPPORTED;
   const trinv_opts o = resolve_opts(opts);
-  if (o.upper) return TRINV_ERR_UNSUPPORTED;
-  if (o.leaf != 0 && o.leaf != 16) return TRINV_ERR_ARG;
-  const size_t es = mode == TRINV_F32 ? 4 : 8;
-  int64_t extent = 0;
+  BatchKey key;
   double flops = 0.0, bytes = 0.0;
-  for (int64_t i = 0; i < batch; ++i) {
-    const int64_t n = n_host[i];
-    if (n < 1 || n > 1024 || off_host[i] < 0) return TRINV_ERR_ARG;
-    extent = std::max<int64_t>(extent, off_host[i] + n * n);
-    flops += (double)n * n * n / 3.0;
-    bytes += es * ((double)n * (n + 1) / 2 + (double)n * n);  // lower triangle in, full X out
-  }
-  if (overlaps(L_packed, (size_t)extent * es, X_packed, (size_t)extent * es)) return TRINV_ERR_ARG;
+  const int chk = check_batch(mode, batch, n_host, n_dev, off_host, off_dev, L_packed, X_packed, status_dev, o, &key,
+                              &flops, &bytes);
+  if (chk != TRINV_OK) return chk;
   Carve c(ws, ws_bytes);
   WsPersistent w = carve_persistent(c, batch);
   if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
@@ -113,12 +169,8 @@ extern "C" int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t
     HIP_TRY(launch_status_to_i32(wl.first_bad, status_dev, batch, s));
   } else {
     ProfLaunch pl(mode == TRINV_F32 ? "f32_batched" : "f64_batched", flops, bytes, s);
-    if (mode == TRINV_F32)
-      HIP_TRY(launch_batched<float>(batch, n_dev, off_dev, (const float*)L_packed, (float*)X_packed, status_dev,
-                                    w.order, w.queue, o.unit_diag, batched_grid<float>(batch), s));
-    else
-      HIP_TRY(launch_batched<double>(batch, n_dev, off_dev, (const double*)L_packed, (double*)X_packed, status_dev,
-                                     w.order, w.queue, o.unit_diag, batched_grid<double>(batch), s));
+    HIP_TRY(launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o.unit_diag,
+                              tuned_config(key), s));
   }
   if (!o.blocking) return TRINV_OK;
   std::vector<int32_t> st((size_t)batch);
@@ -128,5 +180,95 @@ extern "C" int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t
     if (v < 0) return TRINV_ERR_ARG;  // n_dev disagreed with n_host
   for (int32_t v : st)
     if (v > 0) return TRINV_ERR_SINGULAR;
+  return TRINV_OK;
+}
+
+extern "C" int trinv_batched_autotune(int mode, int64_t batch, const int32_t* n_host, const int32_t* n_dev,
+                                      const int64_t* off_host, const int64_t* off_dev, const void* L_packed,
+                                      void* X_packed, int32_t* status_dev, const trinv_opts* opts, void* ws,
+                                      size_t ws_bytes, trinv_stream_t stream, trinv_batched_config* out) {
+  if (out) *out = trinv_batched_config{0, 0, -1.0f};
+  if (batch < 0 || batch > INT32_MAX) return TRINV_ERR_ARG;
+  if (batch == 0) return TRINV_OK;
+  const trinv_opts o = resolve_opts(opts);
+  BatchKey key;
+  double flops = 0.0, bytes = 0.0;
+  const int chk = check_batch(mode, batch, n_host, n_dev, off_host, off_dev, L_packed, X_packed, status_dev, o, &key,
+                              &flops, &bytes);
+  if (chk != TRINV_OK) return chk;
+  Carve c(ws, ws_bytes);
+  WsPersistent w = carve_persistent(c, batch);
+  if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
+  if (level_path(batch, n_host, off_host)) return TRINV_OK;  // the level path has nothing to tune
+  hipStream_t s = (hipStream_t)stream;
+  const int occ = mode == TRINV_F32 ? batched_occupancy<float>(nullptr) : batched_occupancy<double>(nullptr);
+  std::vector<int> per_cu = {1};
+  for (int k = 2; k <= occ; k *= 2) per_cu.push_back(k);
+  if (per_cu.back() != occ) per_cu.push_back(occ);
+  const int wg_from[] = {128, 256, 1024};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return TRINV_ERR_HIP;
+  }
+  PersistentConfig best;
+  float best_ms = -1.0f;
+  hipError_t err = hipSuccess;
+  for (int wf : wg_from) {
+    for (int pc : per_cu) {
+      const PersistentConfig cfg{wf, pc};
+      // one untimed launch, then the fastest of three
+      err = launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o.unit_diag, cfg, s);
+      float ms = -1.0f;
+      for (int r = 0; r < 3 && err == hipSuccess; ++r) {
+        if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
+        if ((err = launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o.unit_diag, cfg,
+                                     s)) != hipSuccess)
+          break;
+        if ((err = hipEventRecord(e1, s)) != hipSuccess) break;
+        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+        float t = 0.0f;
+        if ((err = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) break;
+        if (ms < 0.0f || t < ms) ms = t;
+      }
+      if (err != hipSuccess) break;
+      if (best_ms < 0.0f || ms < best_ms) {
+        best_ms = ms;
+        best = cfg;
+      }
+    }
+    if (err != hipSuccess) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return TRINV_ERR_HIP;
+  {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    g_tuned[key] = best;
+  }
+  // leave X and status from the chosen configuration
+  HIP_TRY(launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o.unit_diag, best, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (out) *out = trinv_batched_config{best.wg_from, best.per_cu, best_ms};
+  return TRINV_OK;
+}
+
+extern "C" int trinv_batched_set_config(int mode, int64_t batch, const int32_t* n_host,
+                                        const trinv_batched_config* cfg) {
+  if (batch <= 0 || batch > INT32_MAX || !n_host || !cfg) return TRINV_ERR_ARG;
+  if (mode != TRINV_F64 && mode != TRINV_F32) return TRINV_ERR_UNSUPPORTED;
+  if (cfg->wg_tile_from < 128 || cfg->wgs_per_cu < 0) return TRINV_ERR_ARG;
+  int64_t s1 = 0, s2 = 0;
+  int nmax = 0;
+  for (int64_t i = 0; i < batch; ++i) {
+    const int64_t n = n_host[i];
+    if (n < 1 || n > 1024) return TRINV_ERR_ARG;
+    s1 += n;
+    s2 += n * n;
+    nmax = std::max<int>(nmax, (int)n);
+  }
+  std::lock_guard<std::mutex> lock(g_tuned_mu);
+  g_tuned[BatchKey(mode, batch, s1, s2, nmax)] = PersistentConfig{cfg->wg_tile_from, cfg->wgs_per_cu};
   return TRINV_OK;
 }

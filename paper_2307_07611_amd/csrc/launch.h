@@ -158,14 +158,22 @@ hipError_t launch_transpose(const T* A, int64_t lda, T* B, int64_t ldb, int64_t 
 
 // Uneven batch in one persistent launch (persistent.hip): a plan kernel sorts
 // the matrices by order into `order` (batch entries) and resets `queue`, then
-// `grid` workgroups invert whole matrices taken from the queue (leaves of 16).
+// `grid` workgroups invert whole matrices taken from the queue (leaves of 16;
+// levels whose blocks have order >= wg_from use 128 x 128 workgroup tiles,
+// smaller ones 32 x 32 wave tiles; wg_from >= 128).
 // status[i]: 0, the 1-based index of the first zero diagonal, or -1 for an
 // order outside [1, 1024].
 template <typename T>
 hipError_t launch_batched(int64_t batch, const int32_t* n_dev, const int64_t* off_dev, const T* L, T* X,
-                          int32_t* status, int32_t* order, uint32_t* queue, int unit, int grid, hipStream_t s);
-// Persistent grid size: resident workgroups on the current device, at most batch.
+                          int32_t* status, int32_t* order, uint32_t* queue, int unit, int grid, int wg_from,
+                          hipStream_t s);
+// Resident workgroups of the persistent kernel per CU (occupancy) and, in
+// *cus, the device's CU count.
 template <typename T>
-int batched_grid(int64_t batch);
+int batched_occupancy(int* cus);
+// Persistent grid size: per_cu workgroups per CU (the occupancy if per_cu is
+// 0 or above it), at most batch.
+template <typename T>
+int batched_grid(int64_t batch, int per_cu);
 
 }  // namespace trinv

@@ -273,13 +273,14 @@ __device__ __forceinline__ void wg_tile(const T* A, int lda, const T* B, int ldb
 }
 
 // All off-diagonal products of one matrix (see the file comment). Levels with
-// blocks of at least 128 use workgroup tiles of 128 (one tile at a time, so
-// the in-place product only has to take its bands bottom-up); smaller levels
-// use independent 32 x 32 wave tiles. Step -1 of a level is T = C A^-1 over
+// blocks of at least wg_from (128 or more; chosen by the autotuner) use
+// workgroup tiles of 128 (one tile at a time, so the in-place product only has
+// to take its bands bottom-up); smaller levels use independent 32 x 32 wave
+// tiles. Step -1 of a level is T = C A^-1 over
 // all merges; step s >= 0 is band (bands - 1 - s) of X21 = -B^-1 T of every
 // merge. Each tile routine has a single call site (keeps register use low).
 template <typename T>
-__device__ __forceinline__ void levels(const T* __restrict__ L, T* X, int n, int b, T* lds) {
+__device__ __forceinline__ void levels(const T* __restrict__ L, T* X, int n, int b, int wg_from, T* lds) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: tile parameters stay scalar
   constexpr int NW = kThreads / 64;
@@ -295,7 +296,7 @@ __device__ __forceinline__ void levels(const T* __restrict__ L, T* X, int n, int
         X[(o + i) * n + o + h + j] = T(0);
       }
     }
-    const bool big = h >= GT;
+    const bool big = h >= wg_from;
     const int TT = big ? GT : WT;
     const int tc = (h + TT - 1) / TT;                           // column tiles of T / X21
     const int tr_full = tc, tr_last = (hb_last + TT - 1) / TT;  // row tiles (bands)
@@ -344,7 +345,8 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_batched(int64_t batch, const int32_t* __restrict__ n_dev,
                                                       const int64_t* __restrict__ off_dev, const T* __restrict__ L,
                                                       T* __restrict__ X, int32_t* __restrict__ status,
-                                                      const int32_t* __restrict__ order, uint32_t* queue, int unit) {
+                                                      const int32_t* __restrict__ order, uint32_t* queue, int unit,
+                                                      int wg_from) {
   // the leaf stage (256 / B leaves of B x (B + 1) elements) or the two
   // staging buffers of the workgroup tiles
   __shared__ T lds[kThreads * 33 > 2 * GBUF ? kThreads * 33 : 2 * GBUF];
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(int64_t batch, const int32
       const T* Lm = L + offu;
       T* Xm = X + offu;
       leaves<T, kLeaf>(Lm, Xm, n, unit, lds, &s_bad);
-      levels<T>(Lm, Xm, n, kLeaf, lds);
+      levels<T>(Lm, Xm, n, kLeaf, wg_from, lds);
     }
     __syncthreads();
     if (tid == 0) status[m] = (n < 1 || n > 1024) ? -1 : (s_bad == INT_MAX ? 0 : s_bad);
@@ -415,18 +417,20 @@ __global__ __launch_bounds__(1024) void k_batched_plan(int64_t batch, const int3
 
 template <typename T>
 hipError_t launch_batched(int64_t batch, const int32_t* n_dev, const int64_t* off_dev, const T* L, T* X,
-                          int32_t* status, int32_t* order, uint32_t* queue, int unit, int grid, hipStream_t s) {
+                          int32_t* status, int32_t* order, uint32_t* queue, int unit, int grid, int wg_from,
+                          hipStream_t s) {
   if (batch <= 0) return hipSuccess;
+  if (wg_from < GT || grid < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_batched_plan, dim3(1), dim3(1024), 0, s, batch, n_dev, order, queue);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_batched<T>, dim3((unsigned)grid), dim3(kThreads), 0, s, batch, n_dev, off_dev, L, X, status,
-                     order, queue, unit);
+                     order, queue, unit, wg_from);
   return hipGetLastError();
 }
 
 template <typename T>
-int batched_grid(int64_t batch) {
+int batched_occupancy(int* cus_out) {
   static int per_cu = -1, cus = 0;
   if (per_cu < 0) {
     int dev = 0;
@@ -436,15 +440,26 @@ int batched_grid(int64_t batch) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batched<T>, kThreads, 0) != hipSuccess || occ < 1) occ = 1;
     per_cu = occ;
   }
-  const int64_t g = (int64_t)cus * per_cu;
+  if (cus_out) *cus_out = cus;
+  return per_cu;
+}
+
+template <typename T>
+int batched_grid(int64_t batch, int per_cu) {
+  int cus = 0;
+  const int occ = batched_occupancy<T>(&cus);
+  const int k = (per_cu >= 1 && per_cu <= occ) ? per_cu : occ;
+  const int64_t g = (int64_t)cus * k;
   return (int)(batch < g ? batch : g);
 }
 
 template hipError_t launch_batched<float>(int64_t, const int32_t*, const int64_t*, const float*, float*, int32_t*,
-                                          int32_t*, uint32_t*, int, int, hipStream_t);
+                                          int32_t*, uint32_t*, int, int, int, hipStream_t);
 template hipError_t launch_batched<double>(int64_t, const int32_t*, const int64_t*, const double*, double*, int32_t*,
-                                           int32_t*, uint32_t*, int, int, hipStream_t);
-template int batched_grid<float>(int64_t);
-template int batched_grid<double>(int64_t);
+                                           int32_t*, uint32_t*, int, int, int, hipStream_t);
+template int batched_occupancy<float>(int*);
+template int batched_occupancy<double>(int*);
+template int batched_grid<float>(int64_t, int);
+template int batched_grid<double>(int64_t, int);
 
 }  // namespace trinv

@@ -210,3 +210,26 @@ def test_sqr_brsi_argument_errors_before_any_launch(lib):
     w = lib.trinv_brsi_workspace_bytes(_lib.F64, 1024, None)
     assert 3 * 1024 * 1024 * 8 <= w <= 5 * 1024 * 1024 * 8
     assert lib.trinv_brsi_workspace_bytes(_lib.F64, 129, None) >= 2 * 130 * 130 * 8
+
+
+def test_batched_tuner_argument_errors(lib):
+    """The autotuner validates like the batched call; pinning a configuration
+    checks its fields (no launch in either)."""
+    from paper_2307_07611_amd import _lib
+
+    cfg = _lib.BatchedConfig(128, 0, -1.0)
+    sizes = np.array([16, 300, 1024], dtype=np.int32)
+    assert lib.trinv_batched_set_config(_lib.F32, 3, sizes.ctypes.data, ctypes.byref(cfg)) == _lib.OK
+    bad = _lib.BatchedConfig(64, 0, -1.0)
+    assert lib.trinv_batched_set_config(_lib.F32, 3, sizes.ctypes.data, ctypes.byref(bad)) == _lib.ERR_ARG
+    assert lib.trinv_batched_set_config(_lib.F32, 3, None, ctypes.byref(cfg)) == _lib.ERR_ARG
+    assert lib.trinv_batched_set_config(_lib.BF16_REFINE, 3, sizes.ctypes.data, ctypes.byref(cfg)) == \
+        _lib.ERR_UNSUPPORTED
+    big = np.array([16, 2000], dtype=np.int32)
+    assert lib.trinv_batched_set_config(_lib.F32, 2, big.ctypes.data, ctypes.byref(cfg)) == _lib.ERR_ARG
+    out = _lib.BatchedConfig()
+    assert lib.trinv_batched_autotune(_lib.F32, 0, None, None, None, None, None, None, None, None, None, 0, None,
+                                      ctypes.byref(out)) == _lib.OK
+    assert out.ms == -1.0
+    assert lib.trinv_batched_autotune(_lib.F32, 3, None, None, None, None, None, None, None, None, None, 0, None,
+                                      ctypes.byref(out)) == _lib.ERR_ARG

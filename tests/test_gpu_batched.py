@@ -213,3 +213,47 @@ def test_uniform_batches(P, dt, n, batch):
     torch.cuda.synchronize()
     assert np.all(st.cpu().numpy() == 0)
     check(mats, unpack(X.cpu().numpy(), offs, sizes), TOL[dt], oracle_every=max(1, batch // 8))
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("wg_from,per_cu", [(128, 1), (256, 2), (1024, 0), (512, 1)])
+def test_pinned_configurations_vs_oracle(P, dt, wg_from, per_cu):
+    """Every configuration the autotuner may choose (and 512) gives a correct
+    inverse of every matrix: the level products switch between 128 x 128
+    workgroup tiles and 32 x 32 wave tiles at wg_from."""
+    import torch
+
+    banner(f"batched {dt} pinned wg_tile_from={wg_from} wgs_per_cu={per_cu}")
+    sizes = np.array(EDGE_SIZES, dtype=np.int32)
+    np_dt = np.float32 if dt == "f32" else np.float64
+    packed, offs, mats = make_batch(sizes, np_dt, seed0=5000)
+    P.batched_set_config(sizes, dt, wg_from, per_cu)
+    L = torch.from_numpy(packed).cuda()
+    X, status = P.tril_inverse_batched(L, sizes, offs, dt)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    check(mats, unpack(X.cpu().numpy(), offs, sizes), TOL[dt], oracle_every=3)
+
+
+def test_autotune_then_graph_vs_oracle(P):
+    """The autotuner times its candidates on an uneven FP32 batch, keeps one of
+    them, leaves that configuration's result in X, and the captured graph that
+    reuses it replays to the same inverses."""
+    import torch
+
+    sizes = synth.batch_sizes(600)
+    banner(f"batched autotune, {len(sizes)} FP32 matrices")
+    packed, offs, mats = make_batch(sizes, np.float32, seed0=7000)
+    g = P.BatchedGraph(sizes, offs, dtype=torch.float32)
+    g.L.copy_(torch.from_numpy(packed).cuda())
+    cfg = g.tune()
+    print(f"autotune: {cfg}", flush=True)
+    assert cfg["wg_tile_from"] in (128, 256, 1024) and cfg["wgs_per_cu"] >= 1 and cfg["ms"] > 0
+    check(mats, unpack(g.X.cpu().numpy(), offs, sizes), TOL["f32"], oracle_every=25)
+    g.X.zero_()
+    g.capture(tune=False)
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(g.status.abs().sum()) == 0
+        check(mats, unpack(g.X.cpu().numpy(), offs, sizes), TOL["f32"], oracle_every=25)
