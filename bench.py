@@ -273,6 +273,20 @@ def brsi_secondary(P, torch, reps):
             "reps": reps}
 
 
+# The paper's own timing of this method (Table tab:combrit: COMBRIT, MATLAB
+# R2021b, sequential, on an Intel i7 machine; seconds, mean of 10 runs) at
+# its largest order, with the effective rate n^3/3 / t. Another machine and
+# a 16x smaller order: context only, not a baseline for this measurement.
+PAPER_CONTEXT = {
+    "source": "Table tab:combrit (COMBRIT; MATLAB R2021b, sequential, Intel i7)",
+    "n": 1024,
+    "seconds": {"beta2": 4.15e-2, "beta4": 3.06e-2, "crit": 3.33},
+    "effective_gflops": {"beta2": round(1024 ** 3 / 3 / 4.15e-2 / 1e9, 2),
+                         "beta4": round(1024 ** 3 / 3 / 3.06e-2 / 1e9, 2),
+                         "crit": round(1024 ** 3 / 3 / 3.33 / 1e9, 4)},
+}
+
+
 def cpu_baseline(L, seconds):
     """The oracle (column recurrence, all host cores via OpenMP) on a bounded
     sample of the same matrix: evenly spaced columns of L^-1."""
@@ -378,6 +392,7 @@ def main():
         "fwd_err_sampled_cols": h["fwd_err_sampled_cols"],
         "paths": {k: {kk: vv for kk, vv in v.items() if kk != "profile"} for k, v in results.items()},
         "kernel_profile": {k: v["profile"] for k, v in results.items()},
+        "paper_context": PAPER_CONTEXT,
     }
     if "bf16_refine" in results and "f64" in results:
         out["speedup_vs_f64_path"] = round(results["f64"]["ms"] / results["bf16_refine"]["ms"], 3)
