@@ -8,9 +8,9 @@
 // (4 x 4 blocks of 32 x 32, 256 FP32 accumulators per lane). Both operands
 // are k-contiguous in memory (B is stored transposed), so a K step is staged
 // by direct global -> LDS 16-byte loads into a ring of LDS stages (at most
-// 160 KB: five stages, or three for the 2-product form at K = 32 per stage),
-// issued one stage short of the ring ahead, and every MFMA operand is one
-// 16-byte LDS read. Lane
+// 160 KB: five stages of K = 32 for one product, three for the 2-product form,
+// two for the 3-product form), issued one stage short of the ring ahead, and
+// every MFMA operand is one 16-byte LDS read. Lane
 // layouts (measured on gfx950): lane l supplies A(l%32, 8(l/32)+e) and
 // B(8(l/32)+e, l%32), e = 0..7, and receives D(8(r/4) + 4(l/32) + r%4, l%32)
 // in register r.
@@ -711,9 +711,9 @@ static hipError_t dispatch_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_
   // panel-blocked planes (zero outside their triangles, no masks)
   if (c.amask == 0 && c.bmask == 0 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoN0Pb &&
       c.khi == kHiM1) {
-    // 3 products: K = 16 per stage, five stages; 2 products: K = 32, three stages
+    // 3 products: K = 32 per stage, two stages; 2 products: K = 32, three stages
     if (c.epi == kLpEpResid && c.nsplit == 3)
-      return go_lp<F16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid>(a, s, total);
+      return go_lp<F16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid, 32>(a, s, total);
     if (c.epi == kLpEpResid && c.nsplit == 2)
       return go_lp<F16, 2, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid, 32>(a, s, total);
     if (c.epi == kLpEpResid && c.nsplit == 1)
