@@ -35,9 +35,9 @@ namespace {
 constexpr int LT = 256;  // workgroup tile (rows and columns)
 constexpr int kTrLd = LT + 8;  // row length of a transposed tile staged in LDS (16-byte rows, fewer bank conflicts)
 
-template <int NSPLIT, int KTW = 0>
+template <int NSPLIT>
 struct LpShape {
-  static constexpr int KT = KTW ? KTW : (NSPLIT == 3 ? 16 : 32);  // K per LDS stage
+  static constexpr int KT = 32;  // K per LDS stage (two MFMA k steps)
   static constexpr int NT = NSPLIT == 1 ? 2 : (NSPLIT == 2 ? 3 : 4);  // staged tiles per stage
   // LDS stages (at most 160 KB): loads run NBUF - 1 stages ahead
   static constexpr int NBUF = 163840 / (NT * 256 * KT * 2) < 5 ? 163840 / (NT * 256 * KT * 2) : 5;
@@ -137,9 +137,9 @@ int64_t gemm_lp_tiles(const GemmBatch& bt, int tiles) {
   return bt.nmerge * tm * tn;
 }
 
-template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI, int KTW>
+template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
 __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
-  typedef LpShape<NSPLIT, KTW> S;
+  typedef LpShape<NSPLIT> S;
   constexpr int KT = S::KT;
   // NBUF stages x NT tiles x TILE elements (all of the CU's LDS); after the
   // main loop its first bytes hold the per-wave partial sums of the residual
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   // (A tile x B tile): A_hi B_hi (1); A_lo B_hi, A_hi B_hi (2);
   // A_hi B_lo, A_lo B_hi, A_hi B_hi (3).
   constexpr int KS = S::KT / 16, NT = S::NT;
-  static_assert(KS == 2 || NSPLIT == 3, "two k steps per stage, or the 3-product stage at K = 16");
+  static_assert(KS == 2, "two k steps per stage");
   u32x4 fr[KS][NT][4];
   auto prod_a = [](int p) constexpr { return NSPLIT == 1 ? 0 : (NSPLIT == 2 ? (p == 0 ? 2 : 0) : (p == 1 ? 2 : 0)); };
   auto prod_b = [](int p) constexpr { return NSPLIT == 3 ? (p == 0 ? 3 : 1) : 1; };
@@ -317,50 +317,27 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   };
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
-  using I2 = std::integral_constant<int, 2>;
-  using I3 = std::integral_constant<int, 3>;
   // A stage is split around the barrier that makes the next stage readable:
-  // its "head" fragments (k step 0; for the 3-product stage A_hi and B_lo)
-  // are read before the stage starts, the rest while the head products run;
-  // after the barrier the next stage's head fragments are read while this
-  // stage's "tail" products (which use only the rest) run.
+  // its "head" fragments (k step 0) are read before the stage starts, the
+  // rest (k step 1) while the head products run; after the barrier the next
+  // stage's head fragments are read while this stage's "tail" products (k
+  // step 1 only) run.
   auto head_reads = [&](const u16* base) __attribute__((always_inline)) {
-    if constexpr (KS == 2) {
-      static_for<0, NT>([&](auto T) { read_tile(base, I0{}, T); });
-    } else {
-      read_tile(base, I0{}, I0{});
-      read_tile(base, I0{}, I3{});
-    }
+    static_for<0, NT>([&](auto T) { read_tile(base, I0{}, T); });
   };
   auto rest_and_head_products = [&](const u16* base) __attribute__((always_inline)) {
-    if constexpr (KS == 2) {
-      static_for<0, NT>([&](auto T) { read_tile(base, I1{}, T); });
-      static_for<0, NSPLIT>([&](auto P) { mma_prod(I0{}, P); });
-      constexpr int RD = 4 * NT, MF = 16 * NSPLIT, Q = MF / RD, REM = MF - Q * RD;
+    static_for<0, NT>([&](auto T) { read_tile(base, I1{}, T); });
+    static_for<0, NSPLIT>([&](auto P) { mma_prod(I0{}, P); });
+    constexpr int RD = 4 * NT, MF = 16 * NSPLIT, Q = MF / RD, REM = MF - Q * RD;
 #pragma unroll
-      for (int g = 0; g < RD; ++g) {
-        __builtin_amdgcn_sched_group_barrier(0x008, Q, 0);  // MFMA
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
-      }
-      if (REM) __builtin_amdgcn_sched_group_barrier(0x008, REM, 0);
-    } else {
-      read_tile(base, I0{}, I2{});
-      read_tile(base, I0{}, I1{});
-      mma_prod(I0{}, I0{});  // A_hi B_lo (head)
-      mma_prod(I0{}, I2{});  // A_hi B_hi (needs B_hi)
-#pragma unroll
-      for (int g = 0; g < 8; ++g) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-      }
-      __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+    for (int g = 0; g < RD; ++g) {
+      __builtin_amdgcn_sched_group_barrier(0x008, Q, 0);  // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
     }
+    if (REM) __builtin_amdgcn_sched_group_barrier(0x008, REM, 0);
   };
   auto tail_products = [&]() __attribute__((always_inline)) {
-    if constexpr (KS == 2)
-      static_for<0, NSPLIT>([&](auto P) { mma_prod(I1{}, P); });
-    else
-      mma_prod(I0{}, I1{});  // A_lo B_hi
+    static_for<0, NSPLIT>([&](auto P) { mma_prod(I1{}, P); });
   };
 
   // NBUF-stage pipeline: stage st lives in buffer st % NBUF. The loads of
@@ -682,11 +659,11 @@ static int64_t lp_grid(const GemmBatch& bt, int tiles) {
   return (nblk + kNumXcd - 1) / kNumXcd * kNumXcd * 16;
 }
 
-template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI, int KTW = 0>
+template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
 static hipError_t go_lp(const LpGemmArgs& a, hipStream_t s, int64_t total) {
-  typedef LpShape<NSPLIT, KTW> S;
+  typedef LpShape<NSPLIT> S;
   const size_t lds = (size_t)S::NBUF * S::NT * S::TILE * sizeof(unsigned short);
-  auto k = k_gemm_lp<F16, NSPLIT, AM, BM, TILES, ORDER, KLO, KHI, EPI, KTW>;
+  auto k = k_gemm_lp<F16, NSPLIT, AM, BM, TILES, ORDER, KLO, KHI, EPI>;
   static bool attr_set = false;  // per instantiation
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -711,11 +688,11 @@ static hipError_t dispatch_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_
   // panel-blocked planes (zero outside their triangles, no masks)
   if (c.amask == 0 && c.bmask == 0 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoN0Pb &&
       c.khi == kHiM1) {
-    // 3 products: K = 32 per stage, two stages; 2 products: K = 32, three stages
+    // K = 32 per stage: two stages for 3 products, three for 2 products
     if (c.epi == kLpEpResid && c.nsplit == 3)
-      return go_lp<F16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid, 32>(a, s, total);
+      return go_lp<F16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid>(a, s, total);
     if (c.epi == kLpEpResid && c.nsplit == 2)
-      return go_lp<F16, 2, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid, 32>(a, s, total);
+      return go_lp<F16, 2, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid>(a, s, total);
     if (c.epi == kLpEpResid && c.nsplit == 1)
       return go_lp<F16, 1, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid>(a, s, total);
     if (c.epi == kLpEpCorr && c.nsplit == 1)
