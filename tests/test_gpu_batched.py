@@ -216,11 +216,12 @@ def test_uniform_batches(P, dt, n, batch):
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-@pytest.mark.parametrize("wg_from,per_cu", [(128, 1), (256, 2), (1024, 0), (512, 1)])
+@pytest.mark.parametrize("wg_from,per_cu", [(128, 1), (256, 2), (1024, 0), (512, 1), (256, 64)])
 def test_pinned_configurations_vs_oracle(P, dt, wg_from, per_cu):
     """Every configuration the autotuner may choose (and 512) gives a correct
     inverse of every matrix: the level products switch between 128 x 128
-    workgroup tiles and 32 x 32 wave tiles at wg_from."""
+    workgroup tiles and 32 x 32 wave tiles at wg_from; a workgroup count per
+    CU above the occupancy limit runs at that limit."""
     import torch
 
     banner(f"batched {dt} pinned wg_tile_from={wg_from} wgs_per_cu={per_cu}")
@@ -257,3 +258,25 @@ def test_autotune_then_graph_vs_oracle(P):
         torch.cuda.synchronize()
         assert int(g.status.abs().sum()) == 0
         check(mats, unpack(g.X.cpu().numpy(), offs, sizes), TOL["f32"], oracle_every=25)
+
+
+def test_autotune_f64_uneven(P):
+    """The tuner on an FP64 batch: a candidate configuration, correct results."""
+    import torch
+
+    sizes = np.array([17, 300, 64, 1024, 129, 512, 5, 256] * 8, dtype=np.int32)
+    banner(f"batched autotune, {len(sizes)} FP64 matrices")
+    packed, offs, mats = make_batch(sizes, np.float64, seed0=9000)
+    L = torch.from_numpy(packed).cuda()
+    X = torch.empty_like(L)
+    status = torch.empty(len(sizes), dtype=torch.int32, device="cuda")
+    cfg = P.batched_autotune(L, sizes, offs, "f64", out=X, status=status)
+    torch.cuda.synchronize()
+    print(f"autotune: {cfg}", flush=True)
+    assert cfg["wg_tile_from"] in (128, 256, 1024) and cfg["wgs_per_cu"] >= 1 and cfg["ms"] > 0
+    assert int(status.abs().sum()) == 0
+    check(mats, unpack(X.cpu().numpy(), offs, sizes), TOL["f64"], oracle_every=5)
+    X2, st2 = P.tril_inverse_batched(L, sizes, offs, "f64")
+    torch.cuda.synchronize()
+    assert int(st2.abs().sum()) == 0
+    check(mats, unpack(X2.cpu().numpy(), offs, sizes), TOL["f64"], oracle_every=5)
