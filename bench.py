@@ -311,9 +311,18 @@ def cpu_baseline(L, seconds):
     oracle.tril_inverse_columns(L, cols)
     dt = time.perf_counter() - t0
     fl = col_flops(cols)
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(fl / dt / 1e12, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{count} evenly spaced columns of L^-1 (n={n}), {fl:.3e} flops in {dt:.1f} s",
-            "seconds": round(dt, 2)}
+            "seconds": round(dt, 2), "cpu_model": cpu}
 
 
 def main():
