@@ -369,12 +369,14 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
     HIP_TRY(launch_reduce_sum(w.tile_sq, ntl, w.scal + 0, s));
     HIP_TRY(launch_reduce_sum(w.tile_sqx, ntl, w.scal + 1, s));
     }
+    // the norms, and after the forward the leaves' zero-pivot index, in one
+    // wait for the stream
     double h[3];
+    uint64_t bad = ~0ull;
     HIP_TRY(hipMemcpyAsync(h, w.scal, sizeof(h), hipMemcpyDeviceToHost, s));
+    if (iter == 0) HIP_TRY(hipMemcpyAsync(&bad, w.status, sizeof(bad), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (iter == 0) {
-      uint64_t bad = ~0ull;
-      HIP_TRY(hipMemcpy(&bad, w.status, sizeof(bad), hipMemcpyDeviceToHost));
       if (bad != ~0ull && bad <= (uint64_t)n) {
         if (info) info->first_bad_index = (int64_t)bad;
         return TRINV_ERR_SINGULAR;
