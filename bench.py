@@ -219,6 +219,31 @@ def combrit_secondary(P, torch, Ld, reps):
     return out
 
 
+def factored_secondary(P, torch, reps):
+    """Factored inverse at n = 4096, FP64: L unit lower (seed 3), U upper
+    (seed 4); L^-1 and U^-1 (n^3/3 flops each) and Ainv = U^-1 L^-1
+    (2 n^3/3 flops over the two triangles)."""
+    import synth
+
+    n = 4096
+    L = torch.from_numpy(synth.lower_triangular(n, 3, unit=True)).cuda()
+    U = torch.from_numpy(synth.upper_triangular(n, 4)).cuda()
+    out = {"workload": f"factored inverse A^-1 = U^-1 L^-1 from given factors, FP64 n={n}"}
+    for want in (False, True):
+        run = lambda: P.factored_inverse(L, U, l_unit=True, want_ainv=want, leaf=64, blocking=False)  # noqa: E731
+        run()
+        ms = time_events(torch, run, reps)
+        fl = 2 * n ** 3 / 3 + (2 * n ** 3 / 3 if want else 0.0)
+        out["with_ainv" if want else "factors_only"] = {"ms": round(ms, 4), "tflops": round(fl / ms / 1e9, 3),
+                                                        "frac_fp64_mfma": round(fl / ms / 1e9 / PEAK_TFLOPS["f64"], 4)}
+    Linv, Uinv, Ainv = P.factored_inverse(L, U, l_unit=True, leaf=64)
+    A = L @ U
+    eye = torch.eye(n, dtype=A.dtype, device=A.device)
+    out["rel_inverse_residual"] = float(torch.linalg.norm(Ainv @ A - eye) / n ** 0.5)
+    out["reps"] = reps
+    return out
+
+
 def skul_secondary(P, torch, reps):
     """Algorithm SKUL at n = 4096, FP64: Crout factorization plus S = U^-1,
     K = L^-1 and Ainv = S K; effective rate over 2 n^3 flops (2n^3/3 for the
@@ -412,6 +437,9 @@ def main():
         log("backward 64 x 1024 FP32")
         out["secondary"]["backward"] = backward_secondary(P, torch, 10)
         log(f"backward: {out['secondary']['backward']['backward_ms']} ms")
+        log("factored inverse n=4096 FP64")
+        out["secondary"]["factored"] = factored_secondary(P, torch, 5)
+        log(f"factored: {out['secondary']['factored']}")
         log("SKUL n=4096 FP64")
         out["secondary"]["skul"] = skul_secondary(P, torch, 3)
         log(f"skul: {out['secondary']['skul']}")

@@ -229,7 +229,8 @@ int trinv_tril_inverse_backward(int mode, int64_t batch, int64_t n, const void *
  * Factored inverse from given triangular factors A = L U (Section 5,
  * algorithm SKUL's output statement: with S = U^-1 and K = L^-1,
  * S K = A^-1): Linv = L^-1 (lower), Uinv = U^-1 (upper, computed through the
- * transposed view of U), and, if Ainv != NULL, Ainv = Uinv * Linv (dense).
+ * transposed view of U; L and U^T are inverted together as a batch of two),
+ * and, if Ainv != NULL, Ainv = Uinv * Linv (dense).
  * l_unit / u_unit: take that factor's diagonal as 1. mode: TRINV_F64 or
  * TRINV_F32. All leading dimensions are n. ws: at least
  * trinv_factored_workspace_bytes bytes. info: nullable.

@@ -377,10 +377,48 @@ int trinv_tril_inverse(int mode, int64_t n, const void* L, int64_t ldl, void* X,
 // (i, j) starts at max(i, j) (the Pul product of the paper's cost notation).
 namespace {
 
-WsPlain carve_factored(Carve& c, int mode, int64_t n, int64_t leaf) {
-  // The L and U inversions run one after the other on the same stream and
-  // share the T workspace; only the U pass needs the transposed copies.
-  return carve_plain(c, mode, n, leaf, true);
+// L and U^T are inverted together, as a strided batch of two lower
+// triangles: every level launch then has twice the tiles.
+struct WsFactored {
+  uint64_t* status;
+  void* T;    // level workspace for the batch of two
+  void* In;   // [L, U^T], n x n each
+  void* Out;  // [L^-1, (U^-1)^T]
+};
+
+WsFactored carve_factored(Carve& c, int mode, int64_t n, int64_t leaf) {
+  WsFactored w;
+  const size_t es = mode == TRINV_F32 ? 4 : 8;
+  w.status = c.take<uint64_t>(1);
+  w.T = c.take<char>(es * 2 * (size_t)t_elems(n, leaf));
+  w.In = c.take<char>(es * 2 * (size_t)n * n);
+  w.Out = c.take<char>(es * 2 * (size_t)n * n);
+  return w;
+}
+
+// Linv = L^-1, Uinv = U^-1 through the batch of two (unit diagonals are
+// written as exact ones in the copies, so the batch runs without the flag and
+// forms the same values: X_ii = 1/1, X_ij = -s/1).
+template <typename T>
+hipError_t factored_pair(int64_t n, const T* L, int l_unit, const T* U, int u_unit, T* Linv, T* Uinv, int64_t leaf,
+                         const WsFactored& w, hipStream_t s) {
+  const int64_t nn = n * n;
+  T* in = (T*)w.In;
+  T* out = (T*)w.Out;
+  hipError_t e;
+  if ((e = launch_block_copy<T>(L, n, 0, in, n, 0, n, 1, T(1), s)) != hipSuccess) return e;
+  if ((e = launch_transpose<T>(U, n, in + nn, n, n, s)) != hipSuccess) return e;
+  if (l_unit && (e = launch_set_diag<T>(in, n, n, T(1), s)) != hipSuccess) return e;
+  if (u_unit && (e = launch_set_diag<T>(in + nn, n, n, T(1), s)) != hipSuccess) return e;
+  {
+    const double nl = 2.0 * (double)((n + leaf - 1) / leaf), b = (double)leaf;
+    ProfLaunch pl(sizeof(T) == 8 ? "leaf_f64" : "leaf_f32", nl * b * b * b / 3.0, nl * b * b * sizeof(T), s);
+    e = launch_leaf<T>(n, in, n, out, n, nn, 2, (int)leaf, 0, nullptr, nullptr, 0, 0, 1.0, w.status, 0, s);
+  }
+  if (e != hipSuccess) return e;
+  if ((e = run_levels<T, T>(n, in, n, out, n, nn, 2, leaf, (T*)w.T, s)) != hipSuccess) return e;
+  if ((e = launch_block_copy<T>(out, n, 0, Linv, n, 0, n, 1, T(1), s)) != hipSuccess) return e;
+  return launch_transpose<T>(out + nn, n, Uinv, n, n, s);
 }
 
 template <typename T>
@@ -434,22 +472,17 @@ extern "C" int trinv_factored_inverse(int mode, int64_t n, const void* L, int32_
   if (overlaps(Linv, nb, Uinv, nb) || (Ainv && (overlaps(Ainv, nb, Linv, nb) || overlaps(Ainv, nb, Uinv, nb))))
     return TRINV_ERR_ARG;
   Carve c(ws, ws_bytes);
-  WsPlain w = carve_factored(c, mode, n, leaf);
+  WsFactored w = carve_factored(c, mode, n, leaf);
   if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(launch_fill_u64(w.status, ~0ull, 1, s));
-  trinv_opts ol = o, ou = o;
-  ol.upper = 0;
-  ol.unit_diag = l_unit;
-  ou.upper = 1;
-  ou.unit_diag = u_unit;
   if (mode == TRINV_F64) {
-    HIP_TRY(plain_inverse<double>(n, (const double*)L, n, (double*)Linv, n, ol, leaf, w, s));
-    HIP_TRY(plain_inverse<double>(n, (const double*)U, n, (double*)Uinv, n, ou, leaf, w, s));
+    HIP_TRY(factored_pair<double>(n, (const double*)L, l_unit, (const double*)U, u_unit, (double*)Linv,
+                                  (double*)Uinv, leaf, w, s));
     if (Ainv) HIP_TRY(upper_times_lower<double>(n, (const double*)Uinv, (const double*)Linv, (double*)Ainv, s));
   } else {
-    HIP_TRY(plain_inverse<float>(n, (const float*)L, n, (float*)Linv, n, ol, leaf, w, s));
-    HIP_TRY(plain_inverse<float>(n, (const float*)U, n, (float*)Uinv, n, ou, leaf, w, s));
+    HIP_TRY(factored_pair<float>(n, (const float*)L, l_unit, (const float*)U, u_unit, (float*)Linv, (float*)Uinv,
+                                 leaf, w, s));
     if (Ainv) HIP_TRY(upper_times_lower<float>(n, (const float*)Uinv, (const float*)Linv, (float*)Ainv, s));
   }
   if (!o.blocking) return TRINV_OK;

@@ -178,6 +178,23 @@ template hipError_t launch_block_copy<double>(const double*, int64_t, int64_t, d
 template hipError_t launch_block_copy<float>(const float*, int64_t, int64_t, float*, int64_t, int64_t, int64_t,
                                              int64_t, float, hipStream_t);
 
+// A(i, i) = v for i < n (leading dimension ld).
+template <typename T>
+__global__ void k_set_diag(T* A, int64_t ld, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    A[i * ld + i] = v;
+}
+
+template <typename T>
+hipError_t launch_set_diag(T* A, int64_t ld, int64_t n, T v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL((k_set_diag<T>), dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, A, ld, n, v);
+  return hipGetLastError();
+}
+template hipError_t launch_set_diag<double>(double*, int64_t, int64_t, double, hipStream_t);
+template hipError_t launch_set_diag<float>(float*, int64_t, int64_t, float, hipStream_t);
+
 // dst block b (m x m) = [[src block b (n x n), 0], [0, I]] (n <= m; src null:
 // the identity), blocks at strides sstride / dstride.
 template <typename T>

@@ -127,6 +127,9 @@ hipError_t launch_crout_diag(const T* W, int64_t ldw, int64_t sw, int nb, T* L, 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // out[0] = min over blocks b of (b * m + words[b]) over the set words (all ones = unset).
 hipError_t launch_fold_status(const uint64_t* words, int64_t count, int64_t m, uint64_t* out, hipStream_t s);
+// A(i, i) = v for i < n.
+template <typename T>
+hipError_t launch_set_diag(T* A, int64_t ld, int64_t n, T v, hipStream_t s);
 // dst block b = alpha * src block b for nblocks m x m blocks (block b of src at
 // src + b sstride, leading dimension lds; likewise dst).
 template <typename T>
