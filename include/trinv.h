@@ -68,8 +68,9 @@ typedef enum {
    * (which keeps X lower triangular) until the relative residual
    * ||L X - I||_F / (||L||_F ||X||_F) <= opts->tol. The residual is
    * assembled, stored and reduced in FP64; its O(n^3) strictly-lower product
-   * runs on split BF16 slices, so the whole residual stays accurate to far
-   * below the tolerance. The first iterate keeps the FP64 diagonal 1 / L_ii
+   * runs on split BF16 slices or on FP64 MFMA (opts->resid), and
+   * info->resid_error_est estimates the error this leaves in the reported
+   * residual. The first iterate keeps the FP64 diagonal 1 / L_ii
    * and holds BF16 values below it (the values its products read); with
    * max_iter = 0 that iterate is what X holds on return. */
   TRINV_BF16_REFINE = 2,
@@ -106,32 +107,75 @@ typedef struct {
                         F32, lower, n divisible by beta, ldl == ldx, else
                         TRINV_ERR_ARG / TRINV_ERR_UNSUPPORTED), the diagonal
                         blocks by the binary recursion */
+  int32_t resid;     /* refine modes: precision of the residual's O(n^3)
+                        product, one of trinv_resid_prec (default AUTO) */
 } trinv_opts;
+
+/* Precision of the refinement residual's strictly-lower product N_L N_X
+ * (the O(n^2) diagonal terms are always exact FP64). */
+typedef enum {
+  /* SPLIT when its estimated error (info->resid_error_est) is at most
+   * tol / 2, else FP64; decided once, from the first iterate's norms. */
+  TRINV_RESID_AUTO = 0,
+  /* Low-precision slices hi + lo of both factors, three MFMA products
+   * (two for the first iterate, whose strictly lower part one slice holds
+   * exactly), FP32 accumulation. */
+  TRINV_RESID_SPLIT = 1,
+  /* FP64 MFMA. */
+  TRINV_RESID_FP64 = 2
+} trinv_resid_prec;
 
 typedef struct {
   double rel_residual;     /* ||L X - I||_F / (||L||_F ||X||_F), or -1 if not computed */
-  double resid_error_bound;/* refine modes: bound on the error of rel_residual */
+  /* Refine modes: the estimated error of rel_residual, from a random-walk
+   * model of the split product's rounding errors (errors of the ~n terms of
+   * an entry add like independent random signs):
+   *   0.5 * u^2 * ||N_L||_F ||N_X||_F / (sqrt(n) ||L||_F ||X||_F),
+   * u = 2^-8 (BF16) or 2^-11 (FP16); the constant 0.5 is twice the one
+   * measured on the seeded test matrices. It is an estimate, not a bound:
+   * the stopping rule is rel_residual + resid_error_est <= tol. For the
+   * FP64 product: n 2^-53. */
+  double resid_error_est;
+  /* Refine modes: a worst-case bound on the same error (every rounding at
+   * its largest, in the same direction): slices (3u^2 + 3u^3), FP32
+   * accumulation gamma_m = m 2^-23 / (1 - m 2^-23) over the m = nsplit n
+   * products of an entry, FP64 assembly, FP16 underflow. It holds without
+   * assumptions and is usually orders of magnitude above the actual error,
+   * too loose to certify a residual of 1e-12 at these orders. */
+  double resid_error_bound;
   int32_t iterations;      /* refine modes: corrections applied */
   int64_t first_bad_index; /* 1-based index of the first zero diagonal, 0 = none */
 } trinv_info;
 
 /* Fills *opts with the defaults (leaf 0, unit_diag 0, upper 0, max_iter 4,
- * tol 1e-12, blocking 0, check 0, beta 0). Passing opts == NULL to any call
- * means these defaults. */
+ * tol 1e-12, blocking 0, check 0, beta 0, resid AUTO). Passing opts == NULL
+ * to any call means these defaults. */
 void trinv_default_opts(trinv_opts *opts);
 
 /* Human-readable name of a status code (static storage). */
 const char *trinv_status_string(int status);
 
-/* Bytes of workspace trinv_tril_inverse needs for (mode, n, opts). */
+/* Bytes of workspace trinv_tril_inverse needs for (mode, n, opts); 0 for
+ * n <= 0 and for refine-mode orders above 2^23 - 128 (unsupported: the
+ * low-precision products keep 32-bit byte offsets within 256 rows of a
+ * plane). */
 size_t trinv_workspace_bytes(int mode, int64_t n, const trinv_opts *opts);
 
 /*
- * X = L^-1 for one n x n triangular matrix (lower by default).
+ * X = L^-1 for one n x n triangular matrix (lower by default; with
+ * opts->upper an upper input, whose upper inverse is returned, zeros below
+ * the diagonal: every mode computes it as the transpose of the lower inverse
+ * of U^T, Section 2).
  * mode: a trinv_mode. L: device, FP64 for F64/BF16_REFINE/F16_REFINE, FP32
  * for F32; ldl >= n. X: device, same element type, ldx >= n, written in
  * full. ws/ws_bytes: workspace (see trinv_workspace_bytes). info: nullable.
- * Returns a trinv_status.
+ * Status: with opts->blocking (F64 / F32) or always (refine modes),
+ * TRINV_ERR_SINGULAR for an exact zero diagonal entry and
+ * TRINV_ERR_NONFINITE when X holds a NaN or an infinity (a non-finite
+ * input, or overflow); the refine modes also return
+ * TRINV_ERR_NOT_CONVERGED after opts->max_iter corrections (X then holds
+ * the last iterate, info its residual). Refine modes stop when
+ * info->rel_residual + info->resid_error_est <= opts->tol.
  */
 int trinv_tril_inverse(int mode, int64_t n, const void *L, int64_t ldl, void *X, int64_t ldx,
                        const trinv_opts *opts, void *ws, size_t ws_bytes, trinv_stream_t stream,
@@ -159,10 +203,11 @@ size_t trinv_batched_workspace_bytes(int mode, int64_t batch, const int32_t *n_h
  *     ranges must not overlap (TRINV_ERR_ARG).
  *   status_dev: device int32[batch]; status_dev[i] = 0, or the 1-based index
  *     of the first zero diagonal of matrix i (X_i then holds non-finite
- *     values), or -1 if n_dev[i] is outside [1, 1024].
+ *     values), or -1 if n_dev[i] is outside [1, 1024], or -2 if X_i holds a
+ *     NaN or an infinity (a non-finite input entry, or overflow).
  *   opts: leaf 0 or 16 (else TRINV_ERR_ARG); unit_diag honoured; upper is
  *     TRINV_ERR_UNSUPPORTED; blocking: wait and return TRINV_ERR_SINGULAR if
- *     any matrix is singular.
+ *     any matrix is singular, else TRINV_ERR_NONFINITE if any status is -2.
  *   ws: at least trinv_batched_workspace_bytes bytes, caller-owned.
  * Two launches on `stream`: a one-workgroup plan kernel (sorts the matrices
  * by order, largest first, and resets the queue counter in ws) and one
@@ -231,14 +276,23 @@ int trinv_tril_inverse_backward(int mode, int64_t batch, int64_t n, const void *
  * S K = A^-1): Linv = L^-1 (lower), Uinv = U^-1 (upper, computed through the
  * transposed view of U; L and U^T are inverted together as a batch of two),
  * and, if Ainv != NULL, Ainv = Uinv * Linv (dense).
- * l_unit / u_unit: take that factor's diagonal as 1. mode: TRINV_F64 or
- * TRINV_F32. All leading dimensions are n. ws: at least
- * trinv_factored_workspace_bytes bytes. info: nullable.
+ * L (lower, only its lower triangle read) and U (upper, only its upper
+ * triangle read): device, leading dimensions ldl, ldu >= n. l_unit /
+ * u_unit: take that factor's diagonal as 1. Linv, Uinv, Ainv: device
+ * outputs written in full (zeros outside the triangles of Linv and Uinv),
+ * leading dimensions ldli, ldui, ldai >= n (ldai ignored when Ainv is NULL);
+ * no output may overlap an input or another output (TRINV_ERR_ARG).
+ * mode: TRINV_F64 or TRINV_F32. ws: at least trinv_factored_workspace_bytes
+ * bytes. With opts->blocking: an exact zero diagonal entry gives
+ * TRINV_ERR_SINGULAR with info->first_bad_index = the smallest 1-based i at
+ * which L_ii or U_ii is zero; a NaN or an infinity in an output gives
+ * TRINV_ERR_NONFINITE. info: nullable.
  */
 size_t trinv_factored_workspace_bytes(int mode, int64_t n, const trinv_opts *opts);
-int trinv_factored_inverse(int mode, int64_t n, const void *L, int32_t l_unit, const void *U,
-                           int32_t u_unit, void *Linv, void *Uinv, void *Ainv, const trinv_opts *opts,
-                           void *ws, size_t ws_bytes, trinv_stream_t stream, trinv_info *info);
+int trinv_factored_inverse(int mode, int64_t n, const void *L, int64_t ldl, int32_t l_unit, const void *U,
+                           int64_t ldu, int32_t u_unit, void *Linv, int64_t ldli, void *Uinv, int64_t ldui,
+                           void *Ainv, int64_t ldai, const trinv_opts *opts, void *ws, size_t ws_bytes,
+                           trinv_stream_t stream, trinv_info *info);
 
 /*
  * Algorithm SKUL (Section 5): the Crout factorization A = L U (L lower with
@@ -309,6 +363,32 @@ int trinv_brsi(int mode, int64_t n, const void *A, int64_t lda, void *Ainv, int6
 size_t trinv_residual_workspace_bytes(int mode, int64_t n);
 int trinv_residual(int mode, int64_t n, const void *L, int64_t ldl, const void *X, int64_t ldx,
                    void *ws, size_t ws_bytes, trinv_stream_t stream, double *out_host);
+
+/*
+ * The refinement's residual product on its own (not part of the paper; the
+ * residual R = I - L X of TRINV_BF16_REFINE / TRINV_F16_REFINE): R is
+ * assembled in FP64 from the exact diagonal terms and the strictly-lower
+ * product N_L N_X formed from low-precision slices of both factors (nsplit =
+ * 3: hi*hi + hi*lo + lo*hi; nsplit = 2: hi*hi + lo*hi, valid only when every
+ * strictly-lower entry of X, times the FP16 scale, is exactly representable
+ * in the low-precision type, as in the refinement's first iterate) with FP32
+ * accumulation, the same kernels and epilogue the refinement runs.
+ * mode: TRINV_BF16_REFINE or TRINV_F16_REFINE (FP16: L and X scaled by powers
+ * of two from max |L| and max |X|). L, X: device FP64, lower triangles read,
+ * ldl, ldx >= n. R: device FP32, ldr >= n; its lower triangle receives R
+ * (R is lower triangular); inside the 256 x 256 diagonal tiles the strict
+ * upper part is written as 0, elsewhere it is not touched. No overlap of R
+ * with L or X (TRINV_ERR_ARG). out_host (host, 5 doubles): ||R||_F,
+ * ||tril(L)||_F, ||tril(X)||_F, the estimated error of ||R|| / (||L|| ||X||)
+ * and its worst-case bound (as trinv_info's resid_error_est and
+ * resid_error_bound). ws: trinv_refine_residual_workspace_bytes bytes.
+ * Waits for the GPU. Orders above 2^23 - 128 give TRINV_ERR_UNSUPPORTED (the
+ * workspace query returns 0 for them).
+ */
+size_t trinv_refine_residual_workspace_bytes(int mode, int64_t n);
+int trinv_refine_residual(int mode, int64_t n, const void *L, int64_t ldl, const void *X, int64_t ldx,
+                          int32_t nsplit, float *R, int64_t ldr, void *ws, size_t ws_bytes,
+                          trinv_stream_t stream, double *out_host);
 
 /*
  * Measurement helpers (not part of the method). When profiling is enabled,

@@ -54,6 +54,10 @@ What each function follows, and what pins it (tests/test_oracle_pins.py):
   at n = 16, the 1x1 and 2x2 closed forms, and linearity in G.
 * ``residuals`` -- ||LX - I||_F, ||XL - I||_F, ||L||_F, ||X||_F. Pinned by a
   planted perturbation whose residual has a closed form.
+* ``residual_matrix`` -- R = I - L X entry by entry. Pinned by exact zeros
+  for an integer matrix and its exact integer inverse, and by a planted
+  integer perturbation E of that inverse, whose residual is exactly -L E
+  (checked against a pure-Python triple loop in integers).
 """
 
 from __future__ import annotations
@@ -99,6 +103,8 @@ def _load():
     lib.oracle_tril_inverse_backward_rows.restype = _i64
     lib.oracle_residuals.argtypes = [_i64, _dp, _i64, _dp, _i64, _dp]
     lib.oracle_residuals.restype = None
+    lib.oracle_residual_matrix.argtypes = [_i64, _dp, _i64, _dp, _i64, _dp]
+    lib.oracle_residual_matrix.restype = None
     lib.oracle_residual_columns.argtypes = [_i64, _dp, _i64, _dp, _i64, _lp, _i64, _dp]
     lib.oracle_residual_columns.restype = None
     lib.oracle_sqr.argtypes = [_i64, _dp, _i64, _dp, _dp, _dp]
@@ -324,6 +330,16 @@ def residuals(L, X) -> dict:
         "rel_lx": out[0] / denom if denom else 0.0,
         "rel_xl": out[1] / denom if denom else 0.0,
     }
+
+
+def residual_matrix(L, X) -> np.ndarray:
+    """R = I - tril(L) X in FP64 (X read in full)."""
+    L = _f64(L)
+    X = _f64(X)
+    n = L.shape[0]
+    out = np.empty((n, n))
+    _load().oracle_residual_matrix(n, _p(L), n, _p(X), n, _p(out))
+    return out
 
 
 def residual_columns(L, X, cols) -> np.ndarray:

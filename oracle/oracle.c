@@ -339,6 +339,20 @@ ORACLE_API void oracle_residuals(int64_t n, const double *L, int64_t ldl, const 
   out[3] = sqrt(nx);
 }
 
+/* The residual matrix itself: out(i, j) = [i == j] - sum_{k <= i} L(i, k) X(k, j)
+ * (tril(L) read, X read in full; out n x n, leading dimension n), ascending k. */
+ORACLE_API void oracle_residual_matrix(int64_t n, const double *L, int64_t ldl, const double *X, int64_t ldx,
+                                       double *out) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int64_t k = 0; k <= i; ++k) s += L[i * ldl + k] * X[k * ldx + j];
+      out[i * n + j] = (i == j ? 1.0 : 0.0) - s;
+    }
+  }
+}
+
 /* Squared column norms of L X - I for selected columns (for matrices too
  * large for the full residual): out[c] = ||(L X - I)(:, cols[c])||_2^2. */
 ORACLE_API void oracle_residual_columns(int64_t n, const double *L, int64_t ldl, const double *X,

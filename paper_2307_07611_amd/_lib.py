@@ -17,13 +17,17 @@ MODES = {"f64": F64, "f32": F32, "bf16_refine": BF16_REFINE, "f16_refine": F16_R
 
 OK, ERR_ARG, ERR_SINGULAR, ERR_NONFINITE, ERR_NOT_CONVERGED, ERR_HIP, ERR_UNSUPPORTED, ERR_WORKSPACE = range(8)
 
+RESID_AUTO, RESID_SPLIT, RESID_FP64 = 0, 1, 2
+RESID = {"auto": RESID_AUTO, "split": RESID_SPLIT, "fp64": RESID_FP64}
+
 EXPORTS = [
     "trinv_default_opts", "trinv_status_string", "trinv_workspace_bytes", "trinv_tril_inverse",
     "trinv_batched_workspace_bytes", "trinv_tril_inverse_batched", "trinv_batched_autotune",
     "trinv_batched_set_config",
     "trinv_backward_workspace_bytes",
     "trinv_tril_inverse_backward", "trinv_factored_workspace_bytes", "trinv_factored_inverse",
-    "trinv_residual_workspace_bytes", "trinv_residual", "trinv_profile_enable", "trinv_profile_read",
+    "trinv_residual_workspace_bytes", "trinv_residual", "trinv_refine_residual_workspace_bytes",
+    "trinv_refine_residual", "trinv_profile_enable", "trinv_profile_read",
     "trinv_skul_workspace_bytes", "trinv_skul", "trinv_sqr_workspace_bytes", "trinv_sqr",
     "trinv_brsi_workspace_bytes", "trinv_brsi",
 ]
@@ -37,7 +41,7 @@ class ProfileEntry(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("leaf", ctypes.c_int32), ("unit_diag", ctypes.c_int32), ("upper", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("blocking", ctypes.c_int32),
-                ("check", ctypes.c_int32), ("beta", ctypes.c_int32)]
+                ("check", ctypes.c_int32), ("beta", ctypes.c_int32), ("resid", ctypes.c_int32)]
 
 
 class BatchedConfig(ctypes.Structure):
@@ -45,8 +49,9 @@ class BatchedConfig(ctypes.Structure):
 
 
 class Info(ctypes.Structure):
-    _fields_ = [("rel_residual", ctypes.c_double), ("resid_error_bound", ctypes.c_double),
-                ("iterations", ctypes.c_int32), ("first_bad_index", ctypes.c_int64)]
+    _fields_ = [("rel_residual", ctypes.c_double), ("resid_error_est", ctypes.c_double),
+                ("resid_error_bound", ctypes.c_double), ("iterations", ctypes.c_int32),
+                ("first_bad_index", ctypes.c_int64)]
 
 
 _lib = None
@@ -89,8 +94,9 @@ def load():
     lib.trinv_tril_inverse_backward.restype = ctypes.c_int
     lib.trinv_factored_workspace_bytes.argtypes = [ctypes.c_int, _i64, ctypes.POINTER(Opts)]
     lib.trinv_factored_workspace_bytes.restype = _sz
-    lib.trinv_factored_inverse.argtypes = [ctypes.c_int, _i64, _vp, _i32, _vp, _i32, _vp, _vp, _vp,
-                                           ctypes.POINTER(Opts), _vp, _sz, _vp, ctypes.POINTER(Info)]
+    lib.trinv_factored_inverse.argtypes = [ctypes.c_int, _i64, _vp, _i64, _i32, _vp, _i64, _i32, _vp, _i64, _vp,
+                                           _i64, _vp, _i64, ctypes.POINTER(Opts), _vp, _sz, _vp,
+                                           ctypes.POINTER(Info)]
     lib.trinv_factored_inverse.restype = ctypes.c_int
     lib.trinv_skul_workspace_bytes.argtypes = [ctypes.c_int, _i64, ctypes.POINTER(Opts)]
     lib.trinv_skul_workspace_bytes.restype = _sz
@@ -112,6 +118,11 @@ def load():
     lib.trinv_residual.argtypes = [ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp,
                                    ctypes.POINTER(ctypes.c_double)]
     lib.trinv_residual.restype = ctypes.c_int
+    lib.trinv_refine_residual_workspace_bytes.argtypes = [ctypes.c_int, _i64]
+    lib.trinv_refine_residual_workspace_bytes.restype = _sz
+    lib.trinv_refine_residual.argtypes = [ctypes.c_int, _i64, _vp, _i64, _vp, _i64, _i32, _vp, _i64, _vp, _sz, _vp,
+                                          ctypes.POINTER(ctypes.c_double)]
+    lib.trinv_refine_residual.restype = ctypes.c_int
     lib.trinv_profile_enable.argtypes = [ctypes.c_int]
     lib.trinv_profile_enable.restype = ctypes.c_int
     lib.trinv_profile_read.argtypes = [ctypes.POINTER(ProfileEntry), ctypes.c_int]

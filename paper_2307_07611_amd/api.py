@@ -37,12 +37,14 @@ def _mode_for(t: torch.Tensor, mode):
     return m
 
 
-def _opts(leaf=0, unit_diag=False, upper=False, max_iter=4, tol=1e-12, blocking=True, check=False, beta=0):
+def _opts(leaf=0, unit_diag=False, upper=False, max_iter=4, tol=1e-12, blocking=True, check=False, beta=0,
+          resid="auto"):
     o = _lib.Opts()
     _lib.load().trinv_default_opts(ctypes.byref(o))
     o.leaf, o.unit_diag, o.upper = int(leaf), int(unit_diag), int(upper)
     o.max_iter, o.tol, o.blocking, o.check = int(max_iter), float(tol), int(blocking), int(check)
     o.beta = int(beta)
+    o.resid = _lib.RESID[resid] if isinstance(resid, str) else int(resid)
     return o
 
 
@@ -51,14 +53,16 @@ def _workspace(nbytes: int, device):
 
 
 def _info_dict(info: _lib.Info) -> dict:
-    return {"rel_residual": info.rel_residual, "resid_error_bound": info.resid_error_bound,
-            "iterations": info.iterations, "first_bad_index": info.first_bad_index}
+    return {"rel_residual": info.rel_residual, "resid_error_est": info.resid_error_est,
+            "resid_error_bound": info.resid_error_bound, "iterations": info.iterations,
+            "first_bad_index": info.first_bad_index}
 
 
 def tril_inverse(L: torch.Tensor, mode=None, *, leaf=0, unit_diag=False, upper=False, max_iter=4, tol=1e-12,
-                 blocking=True, check=False, beta=0, out=None, workspace=None, return_info=False):
+                 blocking=True, check=False, beta=0, resid="auto", out=None, workspace=None, return_info=False):
     """X = L^-1 for one triangular matrix (lower; ``upper=True`` for upper).
-    ``beta`` > 2: top level of algorithm COMBRIT on a beta x beta block grid."""
+    ``beta`` > 2: top level of algorithm COMBRIT on a beta x beta block grid.
+    ``resid`` (refine modes): "auto", "split" or "fp64" residual product."""
     _check_dev(L)
     if L.dim() != 2 or L.shape[0] != L.shape[1] or L.stride(1) != 1:
         raise ValueError("L must be a square matrix with unit column stride")
@@ -66,7 +70,7 @@ def tril_inverse(L: torch.Tensor, mode=None, *, leaf=0, unit_diag=False, upper=F
     n = L.shape[0]
     X = out if out is not None else torch.empty((n, n), dtype=L.dtype, device=L.device)
     lib = _lib.load()
-    o = _opts(leaf, unit_diag, upper, max_iter, tol, blocking, check, beta)
+    o = _opts(leaf, unit_diag, upper, max_iter, tol, blocking, check, beta, resid)
     nbytes = lib.trinv_workspace_bytes(m, n, ctypes.byref(o))
     ws = workspace if workspace is not None else _workspace(nbytes, L.device)
     info = _lib.Info()
@@ -98,6 +102,28 @@ def residual(L: torch.Tensor, X: torch.Tensor) -> dict:
     return r
 
 
+def refine_residual(L: torch.Tensor, X: torch.Tensor, mode="bf16_refine", nsplit=3, R=None) -> dict:
+    """R = I - L X by the refinement's split residual product
+    (trinv_refine_residual): returns R (FP32, lower triangle; zeros above
+    it), its norms, the estimated error of the relative residual and its
+    worst-case bound."""
+    _check_dev(L, X)
+    n = L.shape[0]
+    m = _lib.MODES[mode]
+    if R is None:
+        R = torch.zeros((n, n), dtype=torch.float32, device=L.device)
+    lib = _lib.load()
+    ws = _workspace(lib.trinv_refine_residual_workspace_bytes(m, n), L.device)
+    out = (ctypes.c_double * 5)()
+    st = lib.trinv_refine_residual(m, n, L.data_ptr(), L.stride(0), X.data_ptr(), X.stride(0), int(nsplit),
+                                   R.data_ptr(), R.stride(0), ws.data_ptr(), ws.numel(), _stream(), out)
+    if st != _lib.OK:
+        raise _lib.TrinvError(st, "trinv_refine_residual")
+    r = {"R": R, "r": out[0], "norm_l": out[1], "norm_x": out[2], "est": out[3], "bound": out[4]}
+    r["rel"] = r["r"] / (r["norm_l"] * r["norm_x"]) if r["norm_l"] * r["norm_x"] else 0.0
+    return r
+
+
 def tril_inverse_backward(X: torch.Tensor, G: torch.Tensor) -> torch.Tensor:
     """-tril(X^T G X^T) for a matrix or a batch (leading dimension) of matrices."""
     _check_dev(X, G)
@@ -119,21 +145,25 @@ def tril_inverse_backward(X: torch.Tensor, G: torch.Tensor) -> torch.Tensor:
 
 def factored_inverse(L: torch.Tensor, U: torch.Tensor, *, l_unit=False, u_unit=False, want_ainv=True, leaf=0,
                      blocking=True):
-    """(Linv, Uinv, Ainv) with A = L U; Ainv = Uinv Linv (None if not wanted)."""
+    """(Linv, Uinv, Ainv) with A = L U; Ainv = Uinv Linv (None if not wanted).
+    L and U may be row-strided views (unit column stride); the outputs are
+    new contiguous matrices."""
     _check_dev(L, U)
-    L = L.contiguous()
-    U = U.contiguous()
+    for t in (L, U):
+        if t.dim() != 2 or t.shape[0] != t.shape[1] or t.stride(1) != 1:
+            raise ValueError("factored_inverse: L and U must be square matrices with unit column stride")
     m = _mode_for(L, None)
     n = L.shape[0]
-    Linv = torch.empty_like(L)
-    Uinv = torch.empty_like(U)
-    Ainv = torch.empty_like(L) if want_ainv else None
+    Linv = torch.empty((n, n), dtype=L.dtype, device=L.device)
+    Uinv = torch.empty_like(Linv)
+    Ainv = torch.empty_like(Linv) if want_ainv else None
     lib = _lib.load()
     o = _opts(leaf=leaf, blocking=blocking)
     ws = _workspace(lib.trinv_factored_workspace_bytes(m, n, ctypes.byref(o)), L.device)
     info = _lib.Info()
-    st = lib.trinv_factored_inverse(m, n, L.data_ptr(), int(l_unit), U.data_ptr(), int(u_unit), Linv.data_ptr(),
-                                    Uinv.data_ptr(), Ainv.data_ptr() if Ainv is not None else None,
+    st = lib.trinv_factored_inverse(m, n, L.data_ptr(), max(L.stride(0), 1), int(l_unit), U.data_ptr(),
+                                    max(U.stride(0), 1), int(u_unit), Linv.data_ptr(), n, Uinv.data_ptr(), n,
+                                    Ainv.data_ptr() if Ainv is not None else None, n,
                                     ctypes.byref(o), ws.data_ptr(), ws.numel(), _stream(), ctypes.byref(info))
     if st != _lib.OK:
         raise _lib.TrinvError(st, "trinv_factored_inverse", _info_dict(info))
@@ -172,7 +202,7 @@ def tril_inverse_batched(L_packed: torch.Tensor, sizes, offsets=None, mode=None,
     st = lib.trinv_tril_inverse_batched(m, batch, sizes_np.ctypes.data, n_dev.data_ptr(), off_np.ctypes.data,
                                         off_dev.data_ptr(), L_packed.data_ptr(), X.data_ptr(), status.data_ptr(),
                                         ctypes.byref(o), ws.data_ptr(), ws.numel(), _stream())
-    if st != _lib.OK and st != _lib.ERR_SINGULAR:
+    if st not in (_lib.OK, _lib.ERR_SINGULAR, _lib.ERR_NONFINITE):  # those two: per matrix, in ``status``
         raise _lib.TrinvError(st, "trinv_tril_inverse_batched")
     return X, status
 
@@ -380,12 +410,20 @@ class TrilInverse(torch.autograd.Function):
 
 
 def batched_uniform_inverse(L: torch.Tensor, mode=None) -> torch.Tensor:
-    """Inverse of a (batch, n, n) stack of lower-triangular matrices."""
+    """Inverse of a (batch, n, n) stack of lower-triangular matrices. Raises
+    TrinvError (ERR_SINGULAR / ERR_NONFINITE) naming the offending matrices
+    if any of them has an exact zero diagonal entry or a non-finite inverse."""
     _check_dev(L)
     L = L.contiguous()
     batch, n = L.shape[0], L.shape[-1]
     sizes = [n] * batch
     X, status = tril_inverse_batched(L.view(-1), sizes, mode=mode)
+    st = status.cpu()
+    if bool((st != 0).any()):
+        bad = torch.nonzero(st != 0).flatten().tolist()
+        code = _lib.ERR_SINGULAR if bool((st[bad] > 0).any()) else _lib.ERR_NONFINITE
+        raise _lib.TrinvError(code, "batched_uniform_inverse",
+                              {"matrices": bad, "status": [int(st[i]) for i in bad]})
     return X.view(batch, n, n)
 
 

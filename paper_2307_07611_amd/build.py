@@ -41,13 +41,21 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> str:
+    """Compile every source and link libtrinv.so. ``incremental``: skip a
+    source whose object is newer than it and than every header."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    headers = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(_ROOT, "include", "*.h"))
+    newest_header = max((os.path.getmtime(h) for h in headers), default=0.0)
     cc = _hipcc()
 
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+        if incremental and os.path.exists(obj):
+            t = os.path.getmtime(obj)
+            if t > os.path.getmtime(src) and t > newest_header:
+                return obj
         cmd = [cc] + _flags() + ["-c", src, "-o", obj]
         out = _run(cmd)
         if verbose and out.strip():

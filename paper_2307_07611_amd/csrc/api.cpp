@@ -149,6 +149,7 @@ constexpr int64_t kPartials = 4096;
 
 struct WsPlain {
   uint64_t* status;
+  unsigned* nonfinite;  // blocking calls: set if X holds a NaN or an infinity
   void* T;
   void* Ut;  // transposed input (upper mode)
   void* Xt;  // transposed output (upper mode)
@@ -158,6 +159,7 @@ WsPlain carve_plain(Carve& c, int mode, int64_t n, int64_t leaf, bool upper) {
   WsPlain w;
   const size_t es = mode == TRINV_F32 ? 4 : 8;
   w.status = c.take<uint64_t>(1);
+  w.nonfinite = c.take<unsigned>(1);
   w.T = c.take<char>(es * (size_t)t_elems(n, leaf));
   w.Ut = upper ? (void*)c.take<char>(es * (size_t)n * n) : nullptr;
   w.Xt = upper ? (void*)c.take<char>(es * (size_t)n * n) : nullptr;
@@ -291,6 +293,7 @@ size_t trinv_workspace_bytes(int mode, int64_t n, const trinv_opts* opts) {
   Carve c(nullptr, 0);
   if (combrit_beta(o) && n % o.beta == 0) {
     c.take<uint64_t>(1);
+    c.take<unsigned>(1);
     c.take<char>(combrit_workspace_bytes(mode, n, o.beta, leaf));
   } else {
     carve_plain(c, mode, n, leaf, o.upper != 0);
@@ -301,12 +304,7 @@ size_t trinv_workspace_bytes(int mode, int64_t n, const trinv_opts* opts) {
 
 int trinv_tril_inverse(int mode, int64_t n, const void* L, int64_t ldl, void* X, int64_t ldx, const trinv_opts* opts,
                        void* ws, size_t ws_bytes, trinv_stream_t stream, trinv_info* info) {
-  if (info) {
-    info->rel_residual = -1.0;
-    info->resid_error_bound = 0.0;
-    info->iterations = 0;
-    info->first_bad_index = 0;
-  }
+  info_reset(info);
   if (n < 0 || ldl < n || ldx < n) return TRINV_ERR_ARG;
   if (n == 0) return TRINV_OK;
   if (!L || !X) return TRINV_ERR_ARG;
@@ -318,6 +316,7 @@ int trinv_tril_inverse(int mode, int64_t n, const void* L, int64_t ldl, void* X,
   const size_t es = mode == TRINV_F32 ? 4 : 8;
   if (overlaps(L, span_bytes(n, n, ldl, es), X, span_bytes(n, n, ldx, es))) return TRINV_ERR_ARG;
   if (o.beta < 0 || o.beta == 1 || o.beta > 16) return TRINV_ERR_ARG;
+  if (o.resid < TRINV_RESID_AUTO || o.resid > TRINV_RESID_FP64) return TRINV_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
   if ((mode == TRINV_BF16_REFINE || mode == TRINV_F16_REFINE) && combrit_beta(o)) return TRINV_ERR_UNSUPPORTED;
   if (mode == TRINV_BF16_REFINE || mode == TRINV_F16_REFINE)
@@ -331,6 +330,7 @@ int trinv_tril_inverse(int mode, int64_t n, const void* L, int64_t ldl, void* X,
     if (n % o.beta != 0 || ldl != ldx) return TRINV_ERR_ARG;
     if (o.upper) return TRINV_ERR_UNSUPPORTED;
     w.status = c.take<uint64_t>(1);
+    w.nonfinite = c.take<unsigned>(1);
     cw_bytes = combrit_workspace_bytes(mode, n, o.beta, leaf);
     cw = c.take<char>(cw_bytes);
   } else {
@@ -351,10 +351,19 @@ int trinv_tril_inverse(int mode, int64_t n, const void* L, int64_t ldl, void* X,
   else
     HIP_TRY(plain_inverse<float>(n, (const float*)L, ldl, (float*)X, ldx, o, leaf, w, s));
   if (!o.blocking) return TRINV_OK;
+  // a NaN or an infinity in L (or an overflow) shows in X
+  HIP_TRY(launch_zero(w.nonfinite, sizeof(unsigned), s));
+  if (mode == TRINV_F64)
+    HIP_TRY(launch_nonfinite<double>((const double*)X, n, ldx, w.nonfinite, s));
+  else
+    HIP_TRY(launch_nonfinite<float>((const float*)X, n, ldx, w.nonfinite, s));
   int64_t bad = 0;
   int st = wait_status(s, w.status, n, &bad);
   if (info) info->first_bad_index = bad;
   if (st != TRINV_OK) return st;
+  unsigned nf = 0;
+  HIP_TRY(hipMemcpy(&nf, w.nonfinite, sizeof(nf), hipMemcpyDeviceToHost));
+  if (nf) return TRINV_ERR_NONFINITE;
   if (o.check && !o.upper && !o.unit_diag) {
     double r3[3];
     st = (mode == TRINV_F64) ? residual_t<double>(n, (const double*)L, ldl, (const double*)X, ldx, wr, s, r3)
@@ -381,6 +390,7 @@ namespace {
 // triangles: every level launch then has twice the tiles.
 struct WsFactored {
   uint64_t* status;
+  unsigned* nonfinite;
   void* T;    // level workspace for the batch of two
   void* In;   // [L, U^T], n x n each
   void* Out;  // [L^-1, (U^-1)^T]
@@ -390,6 +400,7 @@ WsFactored carve_factored(Carve& c, int mode, int64_t n, int64_t leaf) {
   WsFactored w;
   const size_t es = mode == TRINV_F32 ? 4 : 8;
   w.status = c.take<uint64_t>(1);
+  w.nonfinite = c.take<unsigned>(1);
   w.T = c.take<char>(es * 2 * (size_t)t_elems(n, leaf));
   w.In = c.take<char>(es * 2 * (size_t)n * n);
   w.Out = c.take<char>(es * 2 * (size_t)n * n);
@@ -400,14 +411,15 @@ WsFactored carve_factored(Carve& c, int mode, int64_t n, int64_t leaf) {
 // written as exact ones in the copies, so the batch runs without the flag and
 // forms the same values: X_ii = 1/1, X_ij = -s/1).
 template <typename T>
-hipError_t factored_pair(int64_t n, const T* L, int l_unit, const T* U, int u_unit, T* Linv, T* Uinv, int64_t leaf,
-                         const WsFactored& w, hipStream_t s) {
+hipError_t factored_pair(int64_t n, const T* L, int64_t ldl, int l_unit, const T* U, int64_t ldu, int u_unit,
+                         T* Linv, int64_t ldli, T* Uinv, int64_t ldui, int64_t leaf, const WsFactored& w,
+                         hipStream_t s) {
   const int64_t nn = n * n;
   T* in = (T*)w.In;
   T* out = (T*)w.Out;
   hipError_t e;
-  if ((e = launch_block_copy<T>(L, n, 0, in, n, 0, n, 1, T(1), s)) != hipSuccess) return e;
-  if ((e = launch_transpose<T>(U, n, in + nn, n, n, s)) != hipSuccess) return e;
+  if ((e = launch_block_copy<T>(L, ldl, 0, in, n, 0, n, 1, T(1), s)) != hipSuccess) return e;
+  if ((e = launch_transpose<T>(U, ldu, in + nn, n, n, s)) != hipSuccess) return e;
   if (l_unit && (e = launch_set_diag<T>(in, n, n, T(1), s)) != hipSuccess) return e;
   if (u_unit && (e = launch_set_diag<T>(in + nn, n, n, T(1), s)) != hipSuccess) return e;
   {
@@ -417,16 +429,17 @@ hipError_t factored_pair(int64_t n, const T* L, int l_unit, const T* U, int u_un
   }
   if (e != hipSuccess) return e;
   if ((e = run_levels<T, T>(n, in, n, out, n, nn, 2, leaf, (T*)w.T, s)) != hipSuccess) return e;
-  if ((e = launch_block_copy<T>(out, n, 0, Linv, n, 0, n, 1, T(1), s)) != hipSuccess) return e;
-  return launch_transpose<T>(out + nn, n, Uinv, n, n, s);
+  if ((e = launch_block_copy<T>(out, n, 0, Linv, ldli, 0, n, 1, T(1), s)) != hipSuccess) return e;
+  return launch_transpose<T>(out + nn, n, Uinv, ldui, n, s);
 }
 
 template <typename T>
-hipError_t upper_times_lower(int64_t n, const T* Uinv, const T* Linv, T* Ainv, hipStream_t s) {
+hipError_t upper_times_lower(int64_t n, const T* Uinv, int64_t ldui, const T* Linv, int64_t ldli, T* Ainv,
+                             int64_t ldai, hipStream_t s) {
   GemmArgs<T> g{};
-  g.A = {Uinv, n, 0, 0};
-  g.B = {Linv, n, 0, 0};
-  g.D = {Ainv, n, 0, 0};
+  g.A = {Uinv, ldui, 0, 0};
+  g.B = {Linv, ldli, 0, 0};
+  g.D = {Ainv, ldai, 0, 0};
   g.alpha = 1.0;
   g.amask = 3;  // upper: k >= m
   g.bmask = 1;  // lower: k >= n
@@ -449,47 +462,63 @@ extern "C" size_t trinv_factored_workspace_bytes(int mode, int64_t n, const trin
   return c.used;
 }
 
-extern "C" int trinv_factored_inverse(int mode, int64_t n, const void* L, int32_t l_unit, const void* U,
-                                      int32_t u_unit, void* Linv, void* Uinv, void* Ainv, const trinv_opts* opts,
+extern "C" int trinv_factored_inverse(int mode, int64_t n, const void* L, int64_t ldl, int32_t l_unit,
+                                      const void* U, int64_t ldu, int32_t u_unit, void* Linv, int64_t ldli,
+                                      void* Uinv, int64_t ldui, void* Ainv, int64_t ldai, const trinv_opts* opts,
                                       void* ws, size_t ws_bytes, trinv_stream_t stream, trinv_info* info) {
-  if (info) {
-    info->rel_residual = -1.0;
-    info->resid_error_bound = 0.0;
-    info->iterations = 0;
-    info->first_bad_index = 0;
-  }
-  if (n < 0) return TRINV_ERR_ARG;
+  info_reset(info);
+  if (n < 0 || ldl < n || ldu < n || ldli < n || ldui < n || (Ainv && ldai < n)) return TRINV_ERR_ARG;
   if (n == 0) return TRINV_OK;
   if (!L || !U || !Linv || !Uinv) return TRINV_ERR_ARG;
   if (mode != TRINV_F64 && mode != TRINV_F32) return TRINV_ERR_UNSUPPORTED;
   trinv_opts o = resolve_opts(opts);
   const int64_t leaf = o.leaf ? o.leaf : default_leaf(mode, n);
   if (!valid_leaf(leaf)) return TRINV_ERR_ARG;
-  const size_t es = mode == TRINV_F32 ? 4 : 8, nb = span_bytes(n, n, n, es);
+  const size_t es = mode == TRINV_F32 ? 4 : 8;
+  const size_t bl = span_bytes(n, n, ldl, es), bu = span_bytes(n, n, ldu, es);
   const void* outs[3] = {Linv, Uinv, Ainv};
-  for (const void* p : outs)
-    if (p && (overlaps(p, nb, L, nb) || overlaps(p, nb, U, nb))) return TRINV_ERR_ARG;
-  if (overlaps(Linv, nb, Uinv, nb) || (Ainv && (overlaps(Ainv, nb, Linv, nb) || overlaps(Ainv, nb, Uinv, nb))))
-    return TRINV_ERR_ARG;
+  const size_t ob[3] = {span_bytes(n, n, ldli, es), span_bytes(n, n, ldui, es), span_bytes(n, n, ldai, es)};
+  for (int i = 0; i < 3; ++i) {
+    if (!outs[i]) continue;
+    if (overlaps(outs[i], ob[i], L, bl) || overlaps(outs[i], ob[i], U, bu)) return TRINV_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (outs[j] && overlaps(outs[i], ob[i], outs[j], ob[j])) return TRINV_ERR_ARG;
+  }
   Carve c(ws, ws_bytes);
   WsFactored w = carve_factored(c, mode, n, leaf);
   if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(launch_fill_u64(w.status, ~0ull, 1, s));
   if (mode == TRINV_F64) {
-    HIP_TRY(factored_pair<double>(n, (const double*)L, l_unit, (const double*)U, u_unit, (double*)Linv,
-                                  (double*)Uinv, leaf, w, s));
-    if (Ainv) HIP_TRY(upper_times_lower<double>(n, (const double*)Uinv, (const double*)Linv, (double*)Ainv, s));
+    HIP_TRY(factored_pair<double>(n, (const double*)L, ldl, l_unit, (const double*)U, ldu, u_unit, (double*)Linv,
+                                  ldli, (double*)Uinv, ldui, leaf, w, s));
+    if (Ainv)
+      HIP_TRY(upper_times_lower<double>(n, (const double*)Uinv, ldui, (const double*)Linv, ldli, (double*)Ainv,
+                                        ldai, s));
   } else {
-    HIP_TRY(factored_pair<float>(n, (const float*)L, l_unit, (const float*)U, u_unit, (float*)Linv, (float*)Uinv,
-                                 leaf, w, s));
-    if (Ainv) HIP_TRY(upper_times_lower<float>(n, (const float*)Uinv, (const float*)Linv, (float*)Ainv, s));
+    HIP_TRY(factored_pair<float>(n, (const float*)L, ldl, l_unit, (const float*)U, ldu, u_unit, (float*)Linv, ldli,
+                                 (float*)Uinv, ldui, leaf, w, s));
+    if (Ainv)
+      HIP_TRY(upper_times_lower<float>(n, (const float*)Uinv, ldui, (const float*)Linv, ldli, (float*)Ainv, ldai,
+                                       s));
   }
   if (!o.blocking) return TRINV_OK;
+  HIP_TRY(launch_zero(w.nonfinite, sizeof(unsigned), s));
+  for (int i = 0; i < 3; ++i) {
+    if (!outs[i]) continue;
+    const int64_t ld = i == 0 ? ldli : (i == 1 ? ldui : ldai);
+    if (mode == TRINV_F64)
+      HIP_TRY(launch_nonfinite<double>((const double*)outs[i], n, ld, w.nonfinite, s));
+    else
+      HIP_TRY(launch_nonfinite<float>((const float*)outs[i], n, ld, w.nonfinite, s));
+  }
   int64_t bad = 0;
   const int st = wait_status(s, w.status, n, &bad);
   if (info) info->first_bad_index = bad;
-  return st;
+  if (st != TRINV_OK) return st;
+  unsigned nf = 0;
+  HIP_TRY(hipMemcpy(&nf, w.nonfinite, sizeof(nf), hipMemcpyDeviceToHost));
+  return nf ? TRINV_ERR_NONFINITE : TRINV_OK;
 }
 
 // ---------------------------------------------------------------- adjoint

@@ -39,6 +39,16 @@ struct Level {
   int64_t hA, span, nmerge, hB_last;
 };
 
+// The "nothing computed" state of *info (nullable).
+inline void info_reset(trinv_info* info) {
+  if (!info) return;
+  info->rel_residual = -1.0;
+  info->resid_error_est = 0.0;
+  info->resid_error_bound = 0.0;
+  info->iterations = 0;
+  info->first_bad_index = 0;
+}
+
 trinv_opts resolve_opts(const trinv_opts* o);
 int default_leaf(int mode, int64_t n);
 bool combrit_beta(const trinv_opts& o);
@@ -65,7 +75,11 @@ template <typename T>
 hipError_t combrit_t(int64_t n, const T* L, int64_t ld, T* X, int unit, int beta, int64_t leaf, void* ws,
                      size_t ws_bytes, uint64_t* status, hipStream_t s);
 
-// Mixed-precision path (refine.cpp).
+// Mixed-precision path (refine.cpp). Orders above kMaxRefineOrder are
+// unsupported: the low-precision products keep 32-bit per-lane byte offsets
+// within 256 rows of a plane (256 * 2 bytes * leading dimension < 2^32).
+constexpr int64_t kMaxRefineOrder = ((int64_t)1 << 23) - 128;
+bool refine_order_ok(int64_t n);
 size_t refine_workspace_bytes(int mode, int64_t n, const trinv_opts& o, int64_t leaf);
 int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X, int64_t ldx, const trinv_opts& o,
                    int64_t leaf, void* ws, size_t ws_bytes, hipStream_t s, trinv_info* info);

@@ -167,6 +167,10 @@ extern "C" int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t
                                        (float*)wl.T, s));
     }
     HIP_TRY(launch_status_to_i32(wl.first_bad, status_dev, batch, s));
+    if (mode == TRINV_F64)
+      HIP_TRY(launch_nonfinite_status<double>((const double*)X_packed, n, n * n, batch, status_dev, s));
+    else
+      HIP_TRY(launch_nonfinite_status<float>((const float*)X_packed, n, n * n, batch, status_dev, s));
   } else {
     ProfLaunch pl(mode == TRINV_F32 ? "f32_batched" : "f64_batched", flops, bytes, s);
     HIP_TRY(launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o.unit_diag,
@@ -177,9 +181,11 @@ extern "C" int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t
   HIP_TRY(hipMemcpyAsync(st.data(), status_dev, (size_t)batch * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (int32_t v : st)
-    if (v < 0) return TRINV_ERR_ARG;  // n_dev disagreed with n_host
+    if (v == -1) return TRINV_ERR_ARG;  // n_dev disagreed with n_host
   for (int32_t v : st)
     if (v > 0) return TRINV_ERR_SINGULAR;
+  for (int32_t v : st)
+    if (v == -2) return TRINV_ERR_NONFINITE;
   return TRINV_OK;
 }
 
@@ -272,3 +278,4 @@ extern "C" int trinv_batched_set_config(int mode, int64_t batch, const int32_t* 
   g_tuned[BatchKey(mode, batch, s1, s2, nmax)] = PersistentConfig{cfg->wg_tile_from, cfg->wgs_per_cu};
   return TRINV_OK;
 }
+

@@ -164,12 +164,7 @@ extern "C" size_t trinv_brsi_workspace_bytes(int mode, int64_t n, const trinv_op
 
 extern "C" int trinv_brsi(int mode, int64_t n, const void* A, int64_t lda, void* Ainv, int64_t ldx,
                           const trinv_opts* opts, void* ws, size_t ws_bytes, trinv_stream_t stream, trinv_info* info) {
-  if (info) {
-    info->rel_residual = -1.0;
-    info->resid_error_bound = 0.0;
-    info->iterations = 0;
-    info->first_bad_index = 0;
-  }
+  info_reset(info);
   if (n < 0) return TRINV_ERR_ARG;
   if (n == 0) return TRINV_OK;
   if (!A || !Ainv || lda < n || ldx < n) return TRINV_ERR_ARG;

@@ -306,4 +306,84 @@ hipError_t launch_transpose(const T* A, int64_t lda, T* B, int64_t ldb, int64_t 
 template hipError_t launch_transpose<double>(const double*, int64_t, double*, int64_t, int64_t, hipStream_t);
 template hipError_t launch_transpose<float>(const float*, int64_t, float*, int64_t, int64_t, hipStream_t);
 
+// A = A^T in place: one block per pair of mirrored 32 x 32 tiles (tile row
+// it >= tile column jt), both staged in LDS before either is written.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_inplace(T* A, int64_t lda, int64_t n) {
+  __shared__ T t1[32][33];
+  __shared__ T t2[32][33];
+  const int64_t q = blockIdx.x;
+  int64_t it = (int64_t)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+  while (it * (it + 1) / 2 > q) --it;
+  while ((it + 1) * (it + 2) / 2 <= q) ++it;
+  const int64_t jt = q - it * (it + 1) / 2;
+  const int64_t bi = it * 32, bj = jt * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    if (bi + r < n && bj + tx < n) t1[r][tx] = A[(bi + r) * lda + bj + tx];
+    if (it != jt && bj + r < n && bi + tx < n) t2[r][tx] = A[(bj + r) * lda + bi + tx];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    if (bj + r < n && bi + tx < n) A[(bj + r) * lda + bi + tx] = t1[tx][r];  // (bj + r, bi + tx) <- (bi + tx, bj + r)
+    if (it != jt && bi + r < n && bj + tx < n) A[(bi + r) * lda + bj + tx] = t2[tx][r];
+  }
+}
+
+template <typename T>
+hipError_t launch_transpose_inplace(T* A, int64_t lda, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t t = (n + 31) / 32;
+  hipLaunchKernelGGL((k_transpose_inplace<T>), dim3((unsigned)(t * (t + 1) / 2)), dim3(256), 0, s, A, lda, n);
+  return hipGetLastError();
+}
+template hipError_t launch_transpose_inplace<double>(double*, int64_t, int64_t, hipStream_t);
+template hipError_t launch_transpose_inplace<float>(float*, int64_t, int64_t, hipStream_t);
+
+// *flag |= 1 if the n x n matrix A holds a NaN or an infinity.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nonfinite(const T* __restrict__ A, int64_t n, int64_t lda, int64_t rpb,
+                                                   unsigned* flag) {
+  const int64_t r0 = (int64_t)blockIdx.x * rpb, r1 = r0 + rpb < n ? r0 + rpb : n;
+  bool bad = false;
+  for (int64_t i = r0; i < r1; ++i)
+    for (int64_t j = threadIdx.x; j < n; j += 256) bad |= !isfinite(A[i * lda + j]);
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(flag, 1u);
+}
+
+template <typename T>
+hipError_t launch_nonfinite(const T* A, int64_t n, int64_t lda, unsigned* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t rpb = (n + 4095) / 4096;
+  hipLaunchKernelGGL((k_nonfinite<T>), dim3((unsigned)((n + rpb - 1) / rpb)), dim3(256), 0, s, A, n, lda, rpb, flag);
+  return hipGetLastError();
+}
+template hipError_t launch_nonfinite<double>(const double*, int64_t, int64_t, unsigned*, hipStream_t);
+
+// status[b] = -2 where status[b] == 0 and matrix b (n x n at b * stride)
+// holds a NaN or an infinity; grid (row blocks, batch).
+template <typename T>
+__global__ __launch_bounds__(256) void k_nonfinite_status(const T* __restrict__ X, int64_t n, int64_t stride,
+                                                          int64_t rpb, int32_t* status) {
+  const T* A = X + (int64_t)blockIdx.y * stride;
+  const int64_t r0 = (int64_t)blockIdx.x * rpb, r1 = r0 + rpb < n ? r0 + rpb : n;
+  bool bad = false;
+  for (int64_t i = r0; i < r1; ++i)
+    for (int64_t j = threadIdx.x; j < n; j += 256) bad |= !isfinite(A[i * n + j]);
+  if (__syncthreads_or(bad) && threadIdx.x == 0 && status[blockIdx.y] == 0) status[blockIdx.y] = -2;
+}
+
+template <typename T>
+hipError_t launch_nonfinite_status(const T* X, int64_t n, int64_t stride, int64_t batch, int32_t* status,
+                                   hipStream_t s) {
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  const int64_t rpb = (n + 63) / 64;
+  hipLaunchKernelGGL((k_nonfinite_status<T>), dim3((unsigned)((n + rpb - 1) / rpb), (unsigned)batch), dim3(256), 0,
+                     s, X, n, stride, rpb, status);
+  return hipGetLastError();
+}
+template hipError_t launch_nonfinite_status<double>(const double*, int64_t, int64_t, int64_t, int32_t*, hipStream_t);
+template hipError_t launch_nonfinite_status<float>(const float*, int64_t, int64_t, int64_t, int32_t*, hipStream_t);
+template hipError_t launch_nonfinite<float>(const float*, int64_t, int64_t, unsigned*, hipStream_t);
+
 }  // namespace trinv

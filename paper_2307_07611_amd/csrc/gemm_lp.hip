@@ -201,22 +201,27 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   // Panel-blocked operands (refinement products): the stage of a tile is
   // KT / 16 consecutive 8 KB blocks of its 256-row panel, copied linearly, so
   // the LDS tile is [KT / 16][256][16] with the plane's half exchange.
+  // The tile's first source element (its row or panel base at klo) goes into
+  // the 64-bit base pointer; the per-lane offsets stay inside one 256-row
+  // panel (below 256 ld elements), so they fit 32 bits for any order whose
+  // planes the host accepts.
   constexpr bool PB = (KLO == kLoN0Pb);
-  uint32_t off[S::NT][S::IPW];  // byte offsets of this lane's source chunk, stage 0
+  uint32_t off[S::NT][S::IPW];  // byte offsets of this lane's source chunk from tb[tt], stage 0
 #pragma unroll
   for (int tt = 0; tt < S::NT; ++tt) {
     const bool isb = tt & 1;
     const int64_t ld = isb ? a.ldb : a.lda;
     const int64_t r0 = isb ? n0 : m0, rmax = (isb ? N : M) - 1;
+    tb[tt] += PB ? ((r0 >> 8) * ld + (klo >> 4)) * 4096 : r0 * ld + klo;
 #pragma unroll
     for (int i = 0; i < S::IPW; ++i) {
       if constexpr (PB) {
-        off[tt][i] = (uint32_t)((((r0 >> 8) * ld + (klo >> 4)) * 4096 + (wave * S::IPW + i) * 512 + lane * 8) * 2);
+        off[tt][i] = (uint32_t)(((wave * S::IPW + i) * 512 + lane * 8) * 2);
       } else {
         const int row = (wave * S::IPW + i) * S::RPI + lane / S::CPR;
         const int chunk = (lane % S::CPR) ^ S::swz(row);
         const int64_t grow = imin64(r0 + row, rmax);
-        off[tt][i] = (uint32_t)((grow * ld + klo + 8 * chunk) * 2);
+        off[tt][i] = (uint32_t)(((grow - r0) * ld + 8 * chunk) * 2);
       }
     }
   }
@@ -703,6 +708,10 @@ static hipError_t dispatch_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_
 
 hipError_t launch_gemm_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_t s) {
   if (a.bt.nbatch != 1) return hipErrorInvalidValue;
+  // per-lane source offsets are 32-bit byte offsets within 256 rows of a
+  // row-major plane (panel-blocked planes: within one 8 KB block)
+  if (c.klo != kLoN0Pb && (a.lda < 0 || a.ldb < 0 || 2 * LT * (a.lda > a.ldb ? a.lda : a.ldb) >= (int64_t)1 << 32))
+    return hipErrorInvalidValue;
   const int64_t total = lp_grid(a.bt, c.tiles);
   if (total <= 0) return hipSuccess;
   if (total > 0x7fffffff) return hipErrorInvalidValue;

@@ -158,14 +158,26 @@ hipError_t launch_status_to_i32(const uint64_t* first_bad, int32_t* status, int6
 // B = A^T for an n x n matrix.
 template <typename T>
 hipError_t launch_transpose(const T* A, int64_t lda, T* B, int64_t ldb, int64_t n, hipStream_t s);
+// A = A^T in place for an n x n matrix.
+template <typename T>
+hipError_t launch_transpose_inplace(T* A, int64_t lda, int64_t n, hipStream_t s);
+// *flag |= 1 if the n x n matrix A holds a NaN or an infinity (flag: a
+// device word the caller clears).
+template <typename T>
+hipError_t launch_nonfinite(const T* A, int64_t n, int64_t lda, unsigned* flag, hipStream_t s);
+// status[b] = -2 where status[b] == 0 and the n x n matrix b (leading
+// dimension n, at element b * stride of X) holds a NaN or an infinity.
+template <typename T>
+hipError_t launch_nonfinite_status(const T* X, int64_t n, int64_t stride, int64_t batch, int32_t* status,
+                                   hipStream_t s);
 
 // Uneven batch in one persistent launch (persistent.hip): a plan kernel sorts
 // the matrices by order into `order` (batch entries) and resets `queue`, then
 // `grid` workgroups invert whole matrices taken from the queue (leaves of 16;
 // levels whose blocks have order >= wg_from use 128 x 128 workgroup tiles,
 // smaller ones 32 x 32 wave tiles; wg_from >= 128).
-// status[i]: 0, the 1-based index of the first zero diagonal, or -1 for an
-// order outside [1, 1024].
+// status[i]: 0, the 1-based index of the first zero diagonal, -1 for an
+// order outside [1, 1024], or -2 if a NaN or an infinity was stored into X_i.
 template <typename T>
 hipError_t launch_batched(int64_t batch, const int32_t* n_dev, const int64_t* off_dev, const T* L, T* X,
                           int32_t* status, int32_t* order, uint32_t* queue, int unit, int grid, int wg_from,

@@ -65,7 +65,7 @@ struct PMma<float> {
 template <typename T>
 __device__ __forceinline__ void wave_tile(const T* A, int lda, const T* B, int ldb,
                                           T* D, int ldd, int M, int N, int r0, int c0, int klo,
-                                          int khi, T alpha, int lane) {
+                                          int khi, T alpha, int lane, bool& nf) {
   typedef typename PMma<T>::acc_t acc_t;
   acc_t acc[2][2];
 #pragma unroll
@@ -122,7 +122,9 @@ __device__ __forceinline__ void wave_tile(const T* A, int lda, const T* B, int l
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = r0 + 16 * i + PMma<T>::row(lane, r);
-        if (row < M) D[row * ldd + c] = alpha * acc[i][j][r];
+        const T v = alpha * acc[i][j][r];
+        if (row < M) D[row * ldd + c] = v;
+        nf |= !__builtin_isfinite(v);
       }
     }
 }
@@ -136,7 +138,8 @@ __device__ __forceinline__ void wave_tile(const T* A, int lda, const T* B, int l
 // which keeps one register per row. The whole leaf block of X is written,
 // zeros above the diagonal included.
 template <typename T, int B>
-__device__ __forceinline__ void leaves(const T* __restrict__ L, T* __restrict__ X, int n, int unit, T* lds, int* bad) {
+__device__ __forceinline__ void leaves(const T* __restrict__ L, T* __restrict__ X, int n, int unit, T* lds, int* bad,
+                                       bool& nf) {
   constexpr int G = kThreads / B;
   constexpr int S = B + 1;  // LDS row stride
   const int tid = threadIdx.x;
@@ -172,7 +175,10 @@ __device__ __forceinline__ void leaves(const T* __restrict__ L, T* __restrict__ 
       T* Xl = X + base * n + base + j;
 #pragma unroll
       for (int i = 0; i < B; ++i)
-        if (i < bl) Xl[i * n] = x[i];
+        if (i < bl) {
+          Xl[i * n] = x[i];
+          nf |= !__builtin_isfinite(x[i]);
+        }
     }
     __syncthreads();
   }
@@ -191,7 +197,7 @@ constexpr int GBUF = GT * GSA + KC * GSB;  // elements of one stage
 
 template <typename T>
 __device__ __forceinline__ void wg_tile(const T* A, int lda, const T* B, int ldb, T* D, int ldd, int M, int N, int r0, int c0,
-                        int klo, int khi, T alpha, T* lds) {
+                        int klo, int khi, T alpha, T* lds, bool& nf) {
   typedef typename PMma<T>::acc_t acc_t;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -267,7 +273,9 @@ __device__ __forceinline__ void wg_tile(const T* A, int lda, const T* B, int ldb
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = r0 + wm * 64 + 16 * i + PMma<T>::row(lane, r);
-        if (row < M) D[row * ldd + c] = alpha * acc[i][j][r];
+        const T v = alpha * acc[i][j][r];
+        if (row < M) D[row * ldd + c] = v;
+        nf |= !__builtin_isfinite(v);
       }
     }
 }
@@ -280,7 +288,7 @@ __device__ __forceinline__ void wg_tile(const T* A, int lda, const T* B, int ldb
 // all merges; step s >= 0 is band (bands - 1 - s) of X21 = -B^-1 T of every
 // merge. Each tile routine has a single call site (keeps register use low).
 template <typename T>
-__device__ __forceinline__ void levels(const T* __restrict__ L, T* X, int n, int b, int wg_from, T* lds) {
+__device__ __forceinline__ void levels(const T* __restrict__ L, T* X, int n, int b, int wg_from, T* lds, bool& nf) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: tile parameters stay scalar
   constexpr int NW = kThreads / 64;
@@ -332,9 +340,9 @@ __device__ __forceinline__ void levels(const T* __restrict__ L, T* X, int n, int
           alpha = T(-1);
         }
         if (big)
-          wg_tile<T>(A, n, Bm, n, D, n, hb, h, r0, c0, klo, khi, alpha, lds);
+          wg_tile<T>(A, n, Bm, n, D, n, hb, h, r0, c0, klo, khi, alpha, lds, nf);
         else
-          wave_tile<T>(A, n, Bm, n, D, n, hb, h, r0, c0, klo, khi, alpha, lane);
+          wave_tile<T>(A, n, Bm, n, D, n, hb, h, r0, c0, klo, khi, alpha, lane, nf);
       }
       __syncthreads();
     }
@@ -366,14 +374,15 @@ __global__ __launch_bounds__(kThreads) void k_batched(int64_t batch, const int32
     const int64_t off = off_dev[m];
     const int64_t offu = ((int64_t)__builtin_amdgcn_readfirstlane((int)(off >> 32)) << 32) |
                          (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)off);
+    bool nf = false;  // a NaN or an infinity stored into this matrix's X (and its T blocks)
     if (n >= 1 && n <= 1024) {
       const T* Lm = L + offu;
       T* Xm = X + offu;
-      leaves<T, kLeaf>(Lm, Xm, n, unit, lds, &s_bad);
-      levels<T>(Lm, Xm, n, kLeaf, wg_from, lds);
+      leaves<T, kLeaf>(Lm, Xm, n, unit, lds, &s_bad, nf);
+      levels<T>(Lm, Xm, n, kLeaf, wg_from, lds, nf);
     }
-    __syncthreads();
-    if (tid == 0) status[m] = (n < 1 || n > 1024) ? -1 : (s_bad == INT_MAX ? 0 : s_bad);
+    nf = __syncthreads_or(nf);
+    if (tid == 0) status[m] = (n < 1 || n > 1024) ? -1 : (s_bad != INT_MAX ? s_bad : (nf ? -2 : 0));
     __syncthreads();
   }
 }

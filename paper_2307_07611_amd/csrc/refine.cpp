@@ -166,38 +166,152 @@ hipError_t read_scalar(const double* d, double* h, hipStream_t s) {
   return hipStreamSynchronize(s);
 }
 
+// Frobenius norms of L and X (lower triangles), of their strictly lower
+// parts N_L, N_X and of their diagonals.
+struct Norms {
+  double L, X, nl, nx, dl, dx;
+};
+
+Norms norms_from(const double* h6) {  // h6[2..5]: ||L||^2, ||diag L||^2, ||X||^2, ||diag X||^2
+  Norms q;
+  q.L = std::sqrt(h6[2]);
+  q.dl = std::sqrt(h6[3]);
+  q.X = std::sqrt(h6[4]);
+  q.dx = std::sqrt(h6[5]);
+  q.nl = std::sqrt(std::max(0.0, h6[2] - h6[3]));
+  q.nx = std::sqrt(std::max(0.0, h6[4] - h6[5]));
+  return q;
+}
+
+// Estimated error of rho. Split product: random-walk model (the rounding
+// errors of the ~n terms of an entry add like independent random signs;
+// c = 0.25 measured for BF16 slices, used as 0.5). FP64 product: 2^-53 per
+// entry relative to |N_L||N_X| (no random-walk reduction).
+double resid_est(int f16, bool fp64, double n, const Norms& q) {
+  if (fp64) return std::ldexp(1.0, -53) * q.nl * q.nx / (q.L * q.X);
+  const double u = f16 ? std::ldexp(1.0, -11) : std::ldexp(1.0, -8);
+  return 0.5 * u * u * q.nl * q.nx / (std::sqrt(n) * q.L * q.X);
+}
+
+// Worst-case bound of the same error: every rounding at its largest and in
+// the same direction. Entrywise |dR| <= (slices + gamma_m (1 + 4u)) |N_L||N_X|
+// + FP64 assembly, with || |N_L||N_X| ||_F <= ||N_L||_F ||N_X||_F; FP16 adds
+// the absolute rounding of subnormal slice values (spacing 2^-24 of the
+// scaled value). FP32 accumulation with unit roundoff 2^-23 (covers a
+// truncating add). The FP64 product: gamma_n with 2^-53.
+double resid_bound(int f16, int nsp, bool fp64, double n, const Norms& q, double sL, double sX, double rho) {
+  const double u64 = std::ldexp(1.0, -53);
+  double dr = 3.0 * u64 * (q.nl * q.nx + q.dl * q.nx + q.nl * q.dx) + u64 * std::sqrt(n);  // assembly
+  if (fp64) {
+    const double g = n * u64 / (1.0 - n * u64);
+    dr += g * q.nl * q.nx;
+  } else {
+    const double u = f16 ? std::ldexp(1.0, -11) : std::ldexp(1.0, -8);
+    const double slices = nsp == 2 ? u * u : 3.0 * u * u + 3.0 * u * u * u;
+    const double m = nsp * n, uf = std::ldexp(1.0, -23);
+    const double g = (m * uf < 1.0) ? m * uf / (1.0 - m * uf) : INFINITY;
+    dr += (slices + g * (1.0 + 4.0 * u)) * q.nl * q.nx;
+    if (f16) dr += std::ldexp(1.0, -24) * (1.0 + u) * n * (q.nx / sL + q.nl / sX) * (nsp == 2 ? 1.0 : 2.0);
+  }
+  return dr / (q.L * q.X) + 2.0 * n * n * u64 * rho;  // + the norms' own summation
+}
+
+// R = I - L X with the split product: A roles hi / lo(N_L) (w.PLhi, w.PLlo),
+// B roles hi(N_X)^T (w.PXthi) and, for nsp = 3, lo(N_X)^T (w.PXtlo); FP32 R
+// into R (ldr), R^T in low precision into w.PRt if write_rt, per-tile sums
+// into w.tile_sq / w.tile_sqx, reduced into w.scal[0], w.scal[1].
+hipError_t split_residual(int f16, int nsp, int64_t n, const double* L, int64_t ldl, const double* X, int64_t ldx,
+                          const double* dx, const WsRefine& w, double sL, double sX, float* R, int64_t ldr,
+                          bool write_rt, hipStream_t s) {
+  const double dn = (double)n;
+  GemmBatch bt{1, 1, n, n, n, n, n, n};
+  LpGemmArgs gr{};
+  gr.A_hi = w.PLhi;
+  gr.A_lo = w.PLlo;
+  gr.lda = w.kb;
+  gr.Bt_hi = w.PXthi;
+  gr.Bt_lo = nsp == 3 ? w.PXtlo : nullptr;
+  gr.ldb = w.kb;
+  gr.bt = bt;
+  gr.alpha = 1.0 / (sL * sX);  // acc = (sL N_L)(sX N_X)
+  gr.lp_scale = 1.0;
+  gr.X = (double*)X;
+  gr.ldx = ldx;
+  gr.L = L;
+  gr.ldl = ldl;
+  gr.dL = w.dL;
+  gr.dX = dx;
+  gr.R32 = R;
+  gr.ldr = ldr;
+  gr.Rt = write_rt ? w.PRt : nullptr;
+  gr.ldrt = w.kb;
+  gr.tile_sq = w.tile_sq;
+  gr.tile_sqx = w.tile_sqx;
+  LpConfig cr{f16, nsp, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid};
+  hipError_t e;
+  {
+    ProfLaunch pl(nsp == 2 ? (f16 ? "f16_residual2" : "bf16_residual2") : (f16 ? "f16_residual" : "bf16_residual"),
+                  nsp * tri_flops(dn), dn * dn / 2 * ((nsp + 1) * 2 + 8 + 8 + 4 + 2), s);
+    e = launch_gemm_lp(gr, cr, s);
+  }
+  if (e != hipSuccess) return e;
+  const int64_t ntl = gemm_lp_tiles(bt, kLowerTiles);
+  if ((e = launch_reduce_sum(w.tile_sq, ntl, w.scal + 0, s)) != hipSuccess) return e;
+  return launch_reduce_sum(w.tile_sqx, ntl, w.scal + 1, s);
+}
+
+// Zero bands of the six panel-blocked planes (see launch_zero_band_pb): the
+// residual and correction products read each 256-row panel up to the end of
+// its diagonal 256 x 256 block, up to kBand columns past the 64 x 64 tiles
+// the splits and epilogues write.
+hipError_t zero_bands(const WsRefine& w, int64_t n, hipStream_t s) {
+  void* planes[6] = {w.PLhi, w.PLlo, w.PX, w.PXthi, w.PXtlo, w.PRt};
+  const int right[6] = {1, 1, 1, 0, 0, 0};
+  return launch_zero_band_pb(planes, right, 6, w.kb, n, kBand, s);
+}
+
 }  // namespace
 
 size_t refine_workspace_bytes(int mode, int64_t n, const trinv_opts& o, int64_t leaf) {
   (void)mode;
-  (void)o;
-  if (n <= 0) return 0;
+  if (n <= 0 || !refine_order_ok(n)) return 0;
   Carve c(nullptr, 0);
   carve_refine(c, n, leaf);
+  if (o.upper) c.take<double>((size_t)n * n);  // the transposed input
   return c.used;
 }
 
+bool refine_order_ok(int64_t n) { return n <= kMaxRefineOrder; }
+
 int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X, int64_t ldx, const trinv_opts& o,
                    int64_t leaf, void* ws, size_t ws_bytes, hipStream_t s, trinv_info* info) {
-  if (o.upper) return TRINV_ERR_UNSUPPORTED;
+  if (!refine_order_ok(n)) return TRINV_ERR_UNSUPPORTED;
   if (leaf < 32) return TRINV_ERR_ARG;
+  if (o.resid < TRINV_RESID_AUTO || o.resid > TRINV_RESID_FP64) return TRINV_ERR_ARG;
   const int f16 = mode == TRINV_F16_REFINE;
   Carve c(ws, ws_bytes);
   WsRefine w = carve_refine(c, n, leaf);
+  double* Ut = o.upper ? c.take<double>((size_t)n * n) : nullptr;
   if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
   const int64_t ldp = w.ldp;
   const double dn = (double)n;
 
-  HIP_TRY(launch_fill_u64(w.status, ~0ull, 1, s));
-  // The residual and correction products read each 256-row panel of their
-  // operands up to the end of the panel's diagonal 256 x 256 block, up to
-  // kBand columns past the 64 x 64 tiles the splits and epilogues
-  // write: those bands must hold zeros (nothing writes them afterwards).
-  {
-    void* planes[6] = {w.PLhi, w.PLlo, w.PX, w.PXthi, w.PXtlo, w.PRt};
-    const int right[6] = {1, 1, 1, 0, 0, 0};
-    HIP_TRY(launch_zero_band_pb(planes, right, 6, w.kb, n, kBand, s));
+  // An upper input is inverted through its transpose (Section 2: the two
+  // cases are transposes of each other): L = U^T (lower), X = L^-1, and the
+  // result X^T = U^-1 is transposed in place at the end.
+  if (o.upper) {
+    HIP_TRY(launch_transpose<double>(L, ldl, Ut, n, n, s));
+    L = Ut;
+    ldl = n;
   }
+  auto finish = [&](int st) -> int {
+    if (o.upper && (st == TRINV_OK || st == TRINV_ERR_NOT_CONVERGED))
+      if (launch_transpose_inplace<double>(X, ldx, n, s) != hipSuccess) return TRINV_ERR_HIP;
+    return st;
+  };
+
+  HIP_TRY(launch_fill_u64(w.status, ~0ull, 1, s));
+  HIP_TRY(zero_bands(w, n, s));
   // FP16 planes carry one power-of-two scale each (exact, undone through the
   // epilogues' alpha) so that the values sit in FP16's normal range; BF16 has
   // the exponent range of FP32 and uses 1. L: from max |L|; X during the
@@ -250,16 +364,13 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   GemmBatch bt{1, 1, n, n, n, n, n, n};
   int iter = 0;
   double rho = 0.0;
-  // Precision of the residual's O(n^3) product. The split low-precision
-  // product has a floor: its error relative to ||L|| ||X|| is about
-  //   c * eps_split * ||N_L|| ||N_X|| / (sqrt(n) ||L|| ||X||)
-  // (errors of the ~n terms of each entry add like a random walk; c = 0.25
-  // measured for BF16 slices, eps_split = 2^-16). It is used only when that
-  // estimate, taken with c = 0.5, is at most half the tolerance; otherwise the
-  // residual runs on FP64 MFMA.
-  int resid_fp64 = -1;  // decided once, after the forward, from the norms
-  double floor_est = 0.0;
-  const double eps_split = f16 ? std::ldexp(1.0, -22) : std::ldexp(1.0, -16);
+  // Precision of the residual's O(n^3) product (opts.resid): the split
+  // product's error is estimated by resid_est; AUTO uses it only while that
+  // estimate is at most half the tolerance (decided once, from the first
+  // iterate's norms), otherwise FP64 MFMA.
+  int resid_fp64 = o.resid == TRINV_RESID_FP64 ? 1 : -1;
+  Norms q{};
+  bool have_norms = false;
   // diag(X) in use and the spare buffer a fused correction writes the next
   // one into (it reads the current one).
   double *dx = w.dX, *dx_next = w.dX2;
@@ -284,23 +395,25 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       so.hi_tb = w.PXthi;  // B role of the residual
       so.lo_tb = x_hi_exact ? nullptr : w.PXtlo;
       so.kb = w.kb;
-      if (resid_fp64 < 0) {  // the norms of X for the precision decision, from the split's read
+      if (!have_norms) {  // the norms of X for the precision decision, from the split's read
         so.sq = w.split_sq;
         so.dsq = w.split_dsq;
       }
       HIP_TRY(launch_split(X, ldx, n, f16, so, dx, 0, 1, sX, s));
       px_stale = false;
     }
-    if (resid_fp64 < 0) {
+    if (!have_norms) {
       HIP_TRY(launch_reduce_sum(w.split_sq, split_tiles(n), w.scal + 4, s));
       HIP_TRY(launch_reduce_sum(w.split_dsq, split_tiles(n), w.scal + 5, s));
       double h6[6];
       HIP_TRY(hipMemcpyAsync(h6, w.scal, sizeof(h6), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      const double nl = std::sqrt(std::max(0.0, h6[2] - h6[3])), nx = std::sqrt(std::max(0.0, h6[4] - h6[5]));
-      floor_est = 0.5 * eps_split * nl * nx / (std::sqrt(dn) * std::sqrt(h6[2]) * std::sqrt(h6[4]));
-      resid_fp64 = (floor_est <= 0.5 * o.tol) ? 0 : 1;
+      q = norms_from(h6);
+      have_norms = true;
+      if (resid_fp64 < 0)
+        resid_fp64 = (o.resid == TRINV_RESID_SPLIT || resid_est(f16, false, dn, q) <= 0.5 * o.tol) ? 0 : 1;
     }
+    const int nsp = x_hi_exact ? 2 : 3;
     if (resid_fp64) {
       GemmArgs<double> gf{};
       gf.A = {L, ldl, 0, 0};
@@ -335,39 +448,8 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       HIP_TRY(launch_reduce_sum(w.tile_sq, ntf, w.scal + 0, s));
       HIP_TRY(launch_reduce_sum(w.tile_sqx, ntf, w.scal + 1, s));
     } else {
-    LpGemmArgs gr{};
-    gr.A_hi = w.PLhi;
-    gr.A_lo = w.PLlo;
-    gr.lda = w.kb;
-    gr.Bt_hi = w.PXthi;
-    gr.Bt_lo = x_hi_exact ? nullptr : w.PXtlo;
-    gr.ldb = w.kb;
-    gr.bt = bt;
-    gr.alpha = 1.0 / (sL * sX);  // acc = (sL N_L)(sX N_X)
-    gr.lp_scale = 1.0;
-    gr.X = X;
-    gr.ldx = ldx;
-    gr.L = L;
-    gr.ldl = ldl;
-    gr.dL = w.dL;
-    gr.dX = dx;
-    gr.R32 = w.R32;
-    gr.ldr = n;
-    gr.Rt = f16 ? nullptr : w.PRt;  // FP16: written below, once ||R|| is known
-    gr.ldrt = w.kb;
-    gr.tile_sq = w.tile_sq;
-    gr.tile_sqx = w.tile_sqx;
-    const int nsp = x_hi_exact ? 2 : 3;
-    LpConfig cr{f16, nsp, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid};
-    {
-      ProfLaunch pl(nsp == 2 ? (f16 ? "f16_residual2" : "bf16_residual2") : (f16 ? "f16_residual" : "bf16_residual"),
-                    nsp * tri_flops(dn),
-                    dn * dn / 2 * ((nsp + 1) * 2 + 8 + 8 + 4 + 2), s);
-      HIP_TRY(launch_gemm_lp(gr, cr, s));
-    }
-    const int64_t ntl = gemm_lp_tiles(bt, kLowerTiles);
-    HIP_TRY(launch_reduce_sum(w.tile_sq, ntl, w.scal + 0, s));
-    HIP_TRY(launch_reduce_sum(w.tile_sqx, ntl, w.scal + 1, s));
+      // BF16: R^T leaves in the epilogue; FP16: written below, once ||R|| is known
+      HIP_TRY(split_residual(f16, nsp, n, L, ldl, X, ldx, dx, w, sL, sX, w.R32, n, !f16, s));
     }
     // the norms, and after the forward the leaves' zero-pivot index, in one
     // wait for the stream
@@ -383,16 +465,16 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       }
     }
     rho = std::sqrt(h[0]) / (std::sqrt(h[2]) * std::sqrt(h[1]));
+    const double est = resid_est(f16, resid_fp64 != 0, dn, q);
     if (info) {
       info->rel_residual = rho;
       info->iterations = iter;
-      // Error scale of rho: the floor estimate above for the split product,
-      // n * 2^-53 for the FP64 product.
-      info->resid_error_bound = resid_fp64 ? dn * std::ldexp(1.0, -53) : floor_est;
+      info->resid_error_est = est;
+      info->resid_error_bound = resid_bound(f16, nsp, resid_fp64 != 0, dn, q, sL, sX, rho);
     }
     if (!std::isfinite(rho)) return TRINV_ERR_NONFINITE;
-    if (rho <= o.tol) return TRINV_OK;
-    if (iter >= o.max_iter) return TRINV_ERR_NOT_CONVERGED;
+    if (rho + est <= o.tol) return finish(TRINV_OK);
+    if (iter >= o.max_iter) return finish(TRINV_ERR_NOT_CONVERGED);
     double sR = 1.0;
     if (f16 || resid_fp64) {  // R^T for the correction's B operand (FP16: scaled by ||R||_F)
       if (f16) sR = pow2_scale(std::sqrt(h[0]), 14);
@@ -447,3 +529,77 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
 }
 
 }  // namespace trinv
+
+// ---------------------------------------------------------------- residual helper
+using namespace trinv;
+
+extern "C" size_t trinv_refine_residual_workspace_bytes(int mode, int64_t n) {
+  (void)mode;
+  if (n <= 0 || !refine_order_ok(n)) return 0;
+  Carve c(nullptr, 0);
+  carve_refine(c, n, 64);
+  return c.used;
+}
+
+extern "C" int trinv_refine_residual(int mode, int64_t n, const void* Lv, int64_t ldl, const void* Xv, int64_t ldx,
+                                     int32_t nsplit, float* R, int64_t ldr, void* ws, size_t ws_bytes,
+                                     trinv_stream_t stream, double* out_host) {
+  if (n < 0 || ldl < n || ldx < n || ldr < n || !out_host) return TRINV_ERR_ARG;
+  for (int i = 0; i < 5; ++i) out_host[i] = 0.0;
+  if (n == 0) return TRINV_OK;
+  if (!Lv || !Xv || !R) return TRINV_ERR_ARG;
+  if (mode != TRINV_BF16_REFINE && mode != TRINV_F16_REFINE) return TRINV_ERR_UNSUPPORTED;
+  if (nsplit != 2 && nsplit != 3) return TRINV_ERR_ARG;
+  if (!refine_order_ok(n)) return TRINV_ERR_UNSUPPORTED;
+  const double* L = (const double*)Lv;
+  const double* X = (const double*)Xv;
+  if (overlaps(R, span_bytes(n, n, ldr, 4), L, span_bytes(n, n, ldl, 8)) ||
+      overlaps(R, span_bytes(n, n, ldr, 4), X, span_bytes(n, n, ldx, 8)))
+    return TRINV_ERR_ARG;
+  const int f16 = mode == TRINV_F16_REFINE;
+  Carve c(ws, ws_bytes);
+  WsRefine w = carve_refine(c, n, 64);
+  if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(zero_bands(w, n, s));
+  double sL = 1.0, sX = 1.0;
+  if (f16) {  // as the refinement loop scales them: from max |L| and max |X|
+    double mx = 0.0;
+    HIP_TRY(launch_maxabs<double>(L, n, ldl, 1, 0, w.partial, kPart, w.scal + 6, s));
+    HIP_TRY(read_scalar(w.scal + 6, &mx, s));
+    sL = pow2_scale(mx, 14);
+    HIP_TRY(launch_maxabs<double>(X, n, ldx, 1, 0, w.partial, kPart, w.scal + 6, s));
+    HIP_TRY(read_scalar(w.scal + 6, &mx, s));
+    sX = pow2_scale(mx, 14);
+  }
+  SplitOut sl{};
+  sl.hi_b = w.PLhi;
+  sl.lo_b = w.PLlo;
+  sl.kb = w.kb;
+  sl.sq = w.split_sq;
+  sl.dsq = w.split_dsq;
+  HIP_TRY(launch_split(L, ldl, n, f16, sl, w.dL, 0, 1, sL, s));
+  HIP_TRY(launch_reduce_sum(w.split_sq, split_tiles(n), w.scal + 2, s));
+  HIP_TRY(launch_reduce_sum(w.split_dsq, split_tiles(n), w.scal + 3, s));
+  SplitOut sx{};
+  sx.hi_tb = w.PXthi;
+  sx.lo_tb = nsplit == 3 ? w.PXtlo : nullptr;
+  sx.kb = w.kb;
+  sx.sq = w.split_sq;
+  sx.dsq = w.split_dsq;
+  HIP_TRY(launch_split(X, ldx, n, f16, sx, w.dX, 0, 1, sX, s));
+  HIP_TRY(launch_reduce_sum(w.split_sq, split_tiles(n), w.scal + 4, s));
+  HIP_TRY(launch_reduce_sum(w.split_dsq, split_tiles(n), w.scal + 5, s));
+  HIP_TRY(split_residual(f16, nsplit, n, L, ldl, X, ldx, w.dX, w, sL, sX, R, ldr, !f16, s));
+  double h6[6];
+  HIP_TRY(hipMemcpyAsync(h6, w.scal, sizeof(h6), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const Norms q = norms_from(h6);
+  out_host[0] = std::sqrt(h6[0]);
+  out_host[1] = std::sqrt(h6[2]);
+  out_host[2] = std::sqrt(h6[1]);
+  const double rho = out_host[0] / (out_host[1] * out_host[2]);
+  out_host[3] = resid_est(f16, false, (double)n, q);
+  out_host[4] = resid_bound(f16, nsplit, false, (double)n, q, sL, sX, rho);
+  return TRINV_OK;
+}

@@ -124,12 +124,7 @@ extern "C" size_t trinv_skul_workspace_bytes(int mode, int64_t n, const trinv_op
 extern "C" int trinv_skul(int mode, int64_t n, const void* A, void* L, void* U, void* S, void* K, void* Ainv,
                           const trinv_opts* opts, void* ws, size_t ws_bytes, trinv_stream_t stream,
                           trinv_info* info) {
-  if (info) {
-    info->rel_residual = -1.0;
-    info->resid_error_bound = 0.0;
-    info->iterations = 0;
-    info->first_bad_index = 0;
-  }
+  info_reset(info);
   if (n < 0) return TRINV_ERR_ARG;
   if (n == 0) return TRINV_OK;
   if (!A || !L || !U || !S || !K) return TRINV_ERR_ARG;
@@ -157,7 +152,8 @@ extern "C" int trinv_skul(int mode, int64_t n, const void* A, void* L, void* U, 
     HIP_TRY(skul_lu<float>(n, (const float*)A, (float*)L, (float*)U, w, s));
   trinv_opts of = o;
   of.blocking = 0;
-  const int st = trinv_factored_inverse(mode, n, L, 0, U, 1, K, S, Ainv, &of, w.fws, w.fws_bytes, stream, nullptr);
+  const int st = trinv_factored_inverse(mode, n, L, n, 0, U, n, 1, K, n, S, n, Ainv, n, &of, w.fws, w.fws_bytes,
+                                        stream, nullptr);
   if (st != TRINV_OK) return st;
   if (!o.blocking) return TRINV_OK;
   int64_t bad = 0;

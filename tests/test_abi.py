@@ -62,8 +62,8 @@ def test_default_opts(lib):
 
     o = _lib.Opts()
     lib.trinv_default_opts(ctypes.byref(o))
-    assert (o.leaf, o.unit_diag, o.upper, o.max_iter, o.tol, o.blocking, o.check, o.beta) == \
-        (0, 0, 0, 4, 1e-12, 0, 0, 0)
+    assert (o.leaf, o.unit_diag, o.upper, o.max_iter, o.tol, o.blocking, o.check, o.beta, o.resid) == \
+        (0, 0, 0, 4, 1e-12, 0, 0, 0, _lib.RESID_AUTO)
 
 
 def test_workspace_queries(lib):
@@ -96,9 +96,61 @@ def test_argument_errors_before_any_launch(lib):
     assert info.rel_residual == -1.0 and info.first_bad_index == 0
     assert lib.trinv_tril_inverse_backward(_lib.F64, 1, 4, None, None, None, 16, None, 0, None) == _lib.ERR_ARG
     assert lib.trinv_tril_inverse_backward(_lib.F64, 1, 4, 4096, 8192, 16384, 8, None, 0, None) == _lib.ERR_ARG
-    assert lib.trinv_factored_inverse(_lib.F64, 4, None, 0, None, 0, None, None, None, None, None, 0, None,
-                                      None) == _lib.ERR_ARG
+    fac = lambda n, L, ldl, U, ldu, Li, ldli, Ui, ldui, Ai, ldai: lib.trinv_factored_inverse(  # noqa: E731
+        _lib.F64, n, L, ldl, 0, U, ldu, 0, Li, ldli, Ui, ldui, Ai, ldai, None, None, 0, None, None)
+    assert fac(4, None, 4, None, 4, None, 4, None, 4, None, 4) == _lib.ERR_ARG
+    A, B, C, D, E = 1 << 30, 1 << 31, 1 << 32, 1 << 33, 1 << 34
+    assert fac(4, A, 3, B, 4, C, 4, D, 4, None, 0) == _lib.ERR_ARG   # ldl < n
+    assert fac(4, A, 4, B, 4, C, 4, D, 3, None, 0) == _lib.ERR_ARG   # ldui < n
+    assert fac(4, A, 4, B, 4, C, 4, D, 4, E, 2) == _lib.ERR_ARG      # ldai < n with Ainv
+    assert fac(4, A, 4, B, 4, C, 4, D, 4, None, 0) == _lib.ERR_WORKSPACE  # ldai ignored without Ainv
+    # an output overlapping an input through a leading dimension larger than n
+    assert fac(4, A, 64, B, 4, A + 8 * 5, 4, D, 4, None, 0) == _lib.ERR_ARG
+    assert fac(4, A, 4, B, 4, C, 4, C + 8, 4, None, 0) == _lib.ERR_ARG  # outputs overlap
     assert lib.trinv_residual(_lib.F64, -2, None, 0, None, 0, None, 0, None, None) == _lib.ERR_ARG
+
+
+def test_refine_options_before_any_launch(lib):
+    """The residual-precision option is validated, and refine orders whose
+    low-precision planes would need more than 32-bit per-lane offsets within a
+    256-row panel are rejected (workspace query 0, call UNSUPPORTED) before
+    anything is launched."""
+    from paper_2307_07611_amd import _lib
+
+    o = _lib.Opts()
+    lib.trinv_default_opts(ctypes.byref(o))
+    o.resid = 3
+    assert lib.trinv_tril_inverse(_lib.BF16_REFINE, 64, 1 << 30, 64, 1 << 34, 64, ctypes.byref(o), None, 0, None,
+                                  None) == _lib.ERR_ARG
+    o.resid = -1
+    assert lib.trinv_tril_inverse(_lib.F64, 64, 1 << 30, 64, 1 << 34, 64, ctypes.byref(o), None, 0, None,
+                                  None) == _lib.ERR_ARG
+    for r in (_lib.RESID_AUTO, _lib.RESID_SPLIT, _lib.RESID_FP64):  # valid, but no workspace
+        o.resid = r
+        assert lib.trinv_tril_inverse(_lib.BF16_REFINE, 64, 1 << 30, 64, 1 << 34, 64, ctypes.byref(o), None, 0,
+                                      None, None) == _lib.ERR_WORKSPACE
+    big = (1 << 23) - 127  # first unsupported order
+    assert lib.trinv_workspace_bytes(_lib.BF16_REFINE, big, None) == 0
+    assert lib.trinv_workspace_bytes(_lib.F16_REFINE, big + 1000, None) == 0
+    assert lib.trinv_refine_residual_workspace_bytes(_lib.BF16_REFINE, big) == 0
+    L, X = 1 << 40, (1 << 40) + 8 * big * big + 4096
+    assert lib.trinv_tril_inverse(_lib.BF16_REFINE, big, L, big, X, big, None, 1 << 20, 1 << 20, None, None) == \
+        _lib.ERR_UNSUPPORTED
+    # orders past the old 32-bit wrap of whole-plane offsets (2 n^2 >= 2^32) are supported
+    assert lib.trinv_workspace_bytes(_lib.BF16_REFINE, 46341, None) > 6 * 2 * 46341 * 46341
+    assert lib.trinv_workspace_bytes(_lib.BF16_REFINE, big - 1, None) > 0
+    out = (ctypes.c_double * 5)()
+    rr = lambda mode, n, L, X, nsplit, R, ldr: lib.trinv_refine_residual(  # noqa: E731
+        mode, n, L, n, X, n, nsplit, R, ldr, None, 0, None, out)
+    assert rr(_lib.BF16_REFINE, -1, 1 << 30, 1 << 34, 3, 1 << 36, 1) == _lib.ERR_ARG
+    assert rr(_lib.BF16_REFINE, 0, None, None, 3, None, 0) == _lib.OK
+    assert rr(_lib.F64, 64, 1 << 30, 1 << 34, 3, 1 << 36, 64) == _lib.ERR_UNSUPPORTED
+    assert rr(_lib.BF16_REFINE, 64, 1 << 30, 1 << 34, 4, 1 << 36, 64) == _lib.ERR_ARG
+    assert rr(_lib.BF16_REFINE, 64, 1 << 30, 1 << 34, 3, 1 << 36, 63) == _lib.ERR_ARG
+    assert rr(_lib.BF16_REFINE, 64, 1 << 30, 1 << 34, 3, (1 << 30) + 8, 64) == _lib.ERR_ARG  # R overlaps L
+    assert rr(_lib.F16_REFINE, 64, 1 << 30, 1 << 34, 2, 1 << 36, 64) == _lib.ERR_WORKSPACE
+    assert lib.trinv_refine_residual(_lib.BF16_REFINE, 64, 1 << 30, 64, 1 << 34, 64, 3, 1 << 36, 64, None, 0, None,
+                                     None) == _lib.ERR_ARG
 
 
 def test_batched_argument_errors_before_any_launch(lib):

@@ -272,6 +272,29 @@ def test_residual_planted_perturbation():
     assert cols[q] == pytest.approx(r["lx"] ** 2, rel=1e-12)
 
 
+def test_residual_matrix_planted_integer_perturbation():
+    """R = I - L X entry by entry: exactly zero for an integer unit lower L
+    and its exact integer inverse; for X + E with E an integer matrix (lower
+    and upper entries), exactly -L E, which a pure-Python triple loop over
+    tril(L) gives in integers. A transposed operand, a dropped diagonal term,
+    a sign error or reading triu(L) fails it."""
+    n = 11
+    L = synth.integer_unit_lower(n, seed=5)
+    L_full = L.copy()
+    L_full[np.triu_indices(n, 1)] = 7.0  # garbage above the diagonal: must be ignored
+    X = oracle.tril_inverse(L, unit=True)
+    np.testing.assert_array_equal(oracle.residual_matrix(L_full, X), np.zeros((n, n)))
+    rng = np.random.default_rng(4)
+    E = rng.integers(-3, 4, size=(n, n)).astype(np.float64)
+    R = oracle.residual_matrix(L_full, X + E)
+    Li = [[int(L[i, k]) if k <= i else 0 for k in range(n)] for i in range(n)]
+    Ei = [[int(v) for v in row] for row in E]
+    want = [[-sum(Li[i][k] * Ei[k][j] for k in range(n)) for j in range(n)] for i in range(n)]
+    np.testing.assert_array_equal(R, np.array(want, dtype=np.float64))
+    # its Frobenius norm is the residual metric's
+    assert np.linalg.norm(R) == pytest.approx(oracle.residuals(L_full, X + E)["lx"], rel=1e-14)
+
+
 # ---------------------------------------------------------------- factored inverse
 def test_skul_printed_example(golden):
     """Section 6: from the printed L and U, K = L^{-1} and S = U^{-1} match the
