@@ -130,11 +130,12 @@ typedef struct {
   /* Refine modes: the estimated error of rel_residual, from a random-walk
    * model of the split product's rounding errors (errors of the ~n terms of
    * an entry add like independent random signs):
-   *   0.5 * u^2 * ||N_L||_F ||N_X||_F / (sqrt(n) ||L||_F ||X||_F),
-   * u = 2^-8 (BF16) or 2^-11 (FP16); the constant 0.5 is twice the one
-   * measured on the seeded test matrices. It is an estimate, not a bound:
-   * the stopping rule is rel_residual + resid_error_est <= tol. For the
-   * FP64 product: n 2^-53. */
+   *   (0.5 u^2 + 2^-24 sqrt(n) / 8) ||N_L||_F ||N_X||_F / (sqrt(n) ||L||_F ||X||_F),
+   * u = 2^-8 (BF16) or 2^-11 (FP16): the slices' rounding, then the FP32
+   * accumulation and FP16 subnormals; the constants are about twice the
+   * ones measured on the seeded test matrices. It is an estimate, not a
+   * bound: the stopping rule is rel_residual + resid_error_est <= tol. For
+   * the FP64 product: 2^-53 ||N_L||_F ||N_X||_F / (||L||_F ||X||_F). */
   double resid_error_est;
   /* Refine modes: a worst-case bound on the same error (every rounding at
    * its largest, in the same direction): slices (3u^2 + 3u^3), FP32

@@ -183,14 +183,18 @@ Norms norms_from(const double* h6) {  // h6[2..5]: ||L||^2, ||diag L||^2, ||X||^
   return q;
 }
 
-// Estimated error of rho. Split product: random-walk model (the rounding
-// errors of the ~n terms of an entry add like independent random signs;
-// c = 0.25 measured for BF16 slices, used as 0.5). FP64 product: 2^-53 per
-// entry relative to |N_L||N_X| (no random-walk reduction).
+// Estimated error of rho. Split product: random-walk model, the rounding
+// errors of the ~n terms of an entry adding like independent random signs,
+// so that ||dR||_F is about c ||N_L||_F ||N_X||_F / sqrt(n): slices
+// c = 0.5 u^2 (0.25 u^2 measured for BF16 at n = 16384) plus the FP32
+// accumulation and FP16 subnormal slices, c = 2^-24 sqrt(n) / 8 (FP16 at
+// n = 1000..16384 measured up to 2^-24 sqrt(n) / 12 beyond the slice term).
+// FP64 product: 2^-53 per entry relative to |N_L||N_X|.
 double resid_est(int f16, bool fp64, double n, const Norms& q) {
   if (fp64) return std::ldexp(1.0, -53) * q.nl * q.nx / (q.L * q.X);
   const double u = f16 ? std::ldexp(1.0, -11) : std::ldexp(1.0, -8);
-  return 0.5 * u * u * q.nl * q.nx / (std::sqrt(n) * q.L * q.X);
+  const double c = 0.5 * u * u + std::ldexp(1.0, -24) * std::sqrt(n) / 8.0;
+  return c * q.nl * q.nx / (std::sqrt(n) * q.L * q.X);
 }
 
 // Worst-case bound of the same error: every rounding at its largest and in
