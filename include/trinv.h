@@ -221,6 +221,26 @@ int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t *n_host, c
                                void *X_packed, int32_t *status_dev, const trinv_opts *opts, void *ws,
                                size_t ws_bytes, trinv_stream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same inversion
+ * as trinv_tril_inverse_batched, always by the persistent launch, with its
+ * plan and queue counter in a per-device scratch array of the library
+ * (65536 matrix indices plus the counter, about 256 KB, held by each device
+ * the library runs on until the process ends) instead of a workspace. No
+ * device memory is allocated or freed, by the library or anything it calls.
+ * Arguments, status values and errors as trinv_tril_inverse_batched, without
+ * ws / ws_bytes; batch > 65536 gives TRINV_ERR_ARG. Every call on one device
+ * shares that device's scratch (the plan kernel rewrites the plan and resets
+ * the counter at the start of each call), so calls that overlap on one
+ * device -- on different streams, or from different threads -- race and
+ * must be serialised by the caller.
+ */
+int trinv_tril_inverse_batched_noalloc(int mode, int64_t batch, const int32_t *n_host, const int32_t *n_dev,
+                                       const int64_t *off_host, const int64_t *off_dev, const void *L_packed,
+                                       void *X_packed, int32_t *status_dev, const trinv_opts *opts,
+                                       trinv_stream_t stream);
+
 /* A configuration of the persistent batched launch. */
 typedef struct {
   int32_t wg_tile_from; /* block order from which the level products use 128 x 128

@@ -23,7 +23,7 @@ RESID = {"auto": RESID_AUTO, "split": RESID_SPLIT, "fp64": RESID_FP64}
 EXPORTS = [
     "trinv_default_opts", "trinv_status_string", "trinv_workspace_bytes", "trinv_tril_inverse",
     "trinv_batched_workspace_bytes", "trinv_tril_inverse_batched", "trinv_batched_autotune",
-    "trinv_batched_set_config",
+    "trinv_batched_set_config", "trinv_tril_inverse_batched_noalloc",
     "trinv_backward_workspace_bytes",
     "trinv_tril_inverse_backward", "trinv_factored_workspace_bytes", "trinv_factored_inverse",
     "trinv_residual_workspace_bytes", "trinv_residual", "trinv_refine_residual_workspace_bytes",
@@ -84,6 +84,9 @@ def load():
     lib.trinv_tril_inverse_batched.argtypes = [ctypes.c_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                                ctypes.POINTER(Opts), _vp, _sz, _vp]
     lib.trinv_tril_inverse_batched.restype = ctypes.c_int
+    lib.trinv_tril_inverse_batched_noalloc.argtypes = [ctypes.c_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                                       ctypes.POINTER(Opts), _vp]
+    lib.trinv_tril_inverse_batched_noalloc.restype = ctypes.c_int
     lib.trinv_batched_autotune.argtypes = lib.trinv_tril_inverse_batched.argtypes + [ctypes.POINTER(BatchedConfig)]
     lib.trinv_batched_autotune.restype = ctypes.c_int
     lib.trinv_batched_set_config.argtypes = [ctypes.c_int, _i64, _vp, ctypes.POINTER(BatchedConfig)]

@@ -279,3 +279,40 @@ extern "C" int trinv_batched_set_config(int mode, int64_t batch, const int32_t* 
   return TRINV_OK;
 }
 
+// Allocation-free variant for callers that cannot allocate device memory
+// (graph capture, serving loops): the persistent launch with its plan and
+// queue in the library's per-device scratch instead of a workspace.
+extern "C" int trinv_tril_inverse_batched_noalloc(int mode, int64_t batch, const int32_t* n_host,
+                                                  const int32_t* n_dev, const int64_t* off_host,
+                                                  const int64_t* off_dev, const void* L_packed, void* X_packed,
+                                                  int32_t* status_dev, const trinv_opts* opts,
+                                                  trinv_stream_t stream) {
+  if (batch < 0 || batch > kNoAllocMaxBatch) return TRINV_ERR_ARG;
+  if (batch == 0) return TRINV_OK;
+  const trinv_opts o = resolve_opts(opts);
+  BatchKey key;
+  double flops = 0.0, bytes = 0.0;
+  const int chk = check_batch(mode, batch, n_host, n_dev, off_host, off_dev, L_packed, X_packed, status_dev, o, &key,
+                              &flops, &bytes);
+  if (chk != TRINV_OK) return chk;
+  WsPersistent w{};
+  HIP_TRY(batched_scratch(&w.order, &w.queue));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o.unit_diag,
+                            tuned_config(key), s));
+  if (!o.blocking) return TRINV_OK;
+  // statuses in fixed-size pieces (no host allocation either)
+  int32_t st[1024];
+  int worst = TRINV_OK;
+  for (int64_t i0 = 0; i0 < batch; i0 += 1024) {
+    const int64_t cnt = std::min<int64_t>(1024, batch - i0);
+    HIP_TRY(hipMemcpyAsync(st, status_dev + i0, (size_t)cnt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < cnt; ++i) {
+      if (st[i] == -1) return TRINV_ERR_ARG;  // n_dev disagreed with n_host
+      if (st[i] > 0) worst = TRINV_ERR_SINGULAR;
+      if (st[i] == -2 && worst == TRINV_OK) worst = TRINV_ERR_NONFINITE;
+    }
+  }
+  return worst;
+}

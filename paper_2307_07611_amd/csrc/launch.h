@@ -182,6 +182,13 @@ template <typename T>
 hipError_t launch_batched(int64_t batch, const int32_t* n_dev, const int64_t* off_dev, const T* L, T* X,
                           int32_t* status, int32_t* order, uint32_t* queue, int unit, int grid, int wg_from,
                           hipStream_t s);
+// Device scratch of the allocation-free batched entry point (a file-scope
+// device array, one copy per device): room for the plan of kNoAllocMaxBatch
+// matrices and the queue counter. Returns this device's addresses (looked up
+// once per device).
+constexpr int64_t kNoAllocMaxBatch = 65536;
+constexpr int kMaxDevices = 64;
+hipError_t batched_scratch(int32_t** order, uint32_t** queue);
 // Resident workgroups of the persistent kernel per CU (occupancy) and, in
 // *cus, the device's CU count.
 template <typename T>

@@ -25,10 +25,38 @@
 // captured in a graph.
 #include <limits.h>
 
+#include <mutex>
+
 #include "common.h"
 #include "launch.h"
 
 namespace trinv {
+
+// Scratch of the allocation-free batched entry point: the plan (kNoAllocMaxBatch
+// matrix indices) followed by the queue counter. Each device holds its own copy
+// for the life of the process; host code reaches it only through the address
+// batched_scratch() obtains per device.
+static __device__ __align__(256) int32_t scratch[kNoAllocMaxBatch + 64];
+
+hipError_t batched_scratch(int32_t** order, uint32_t** queue) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *order = (int32_t*)addr[dev];
+  *queue = (uint32_t*)((int32_t*)addr[dev] + kNoAllocMaxBatch);
+  return hipSuccess;
+}
 
 namespace {
 
