@@ -33,13 +33,15 @@ MFMA_KINDS = ("level_T", "level_X21", "residual", "residual2", "correction")
 # HBM traffic per launch measured with hardware counters, keyed by profile class
 # and by a hash of the kernel sources at the time of the measurement.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_n16384.md")
+_LP_SOURCES = ["paper_2307_07611_amd/csrc/gemm_lp.hip", "paper_2307_07611_amd/csrc/lowp.h",
+               "paper_2307_07611_amd/csrc/common.h", "paper_2307_07611_amd/csrc/refine.cpp",
+               "paper_2307_07611_amd/csrc/split.hip", "paper_2307_07611_amd/csrc/launch.h"]
 KERNEL_SOURCES = {
-    "bf16": ["paper_2307_07611_amd/csrc/gemm_lp.hip", "paper_2307_07611_amd/csrc/lowp.h",
-             "paper_2307_07611_amd/csrc/common.h"],
-    "f16": ["paper_2307_07611_amd/csrc/gemm_lp.hip", "paper_2307_07611_amd/csrc/lowp.h",
-            "paper_2307_07611_amd/csrc/common.h"],
+    "bf16": _LP_SOURCES,
+    "f16": _LP_SOURCES,
     "f64": ["paper_2307_07611_amd/csrc/gemm_fp.hip", "paper_2307_07611_amd/csrc/launch.h",
-            "paper_2307_07611_amd/csrc/common.h"],
+            "paper_2307_07611_amd/csrc/common.h", "paper_2307_07611_amd/csrc/api.cpp",
+            "paper_2307_07611_amd/csrc/leaf.hip"],
 }
 
 
@@ -142,6 +144,45 @@ def time_events(torch, fn, reps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def plain_config_secondary(P, torch, n, seed, leaf, reps):
+    """The plain FP64 path on its own configurations: n = 256, leaf 32 (a
+    latency case) and n = 8192, leaf 64 (FP64-MFMA bound, 50% gate)."""
+    import oracle
+    import synth
+
+    L = synth.lower_triangular(n, seed)
+    Ld = torch.from_numpy(L).cuda()
+    X = torch.empty_like(Ld)
+    ws = torch.empty(max(P.workspace_bytes(n, "f64", leaf=leaf), 1), dtype=torch.uint8, device=Ld.device)
+    run = lambda: P.tril_inverse(Ld, "f64", leaf=leaf, out=X, workspace=ws, blocking=False)  # noqa: E731
+    for _ in range(3):
+        run()
+    ms = time_events(torch, run, reps)
+    fl = n ** 3 / 3.0
+    out = {"workload": f"plain FP64 lower-triangular inverse n={n} seed={seed} leaf={leaf}", "ms": round(ms, 5),
+           "tflops": round(fl / ms / 1e9, 4), "frac_fp64_mfma": round(fl / ms / 1e9 / PEAK_TFLOPS["f64"], 4),
+           "reps": reps}
+    r = P.residual(Ld, X)
+    out["rel_residual"] = r["rel"]
+    cols = np.unique(np.linspace(0, n - 2, 6).astype(np.int64))
+    Xo = oracle.tril_inverse_columns(L, cols)
+    Xg = X[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    out.update(fwd_errors(Xg, Xo, cols))
+    if n >= 4096:
+        out["meets_50pct_fp64_peak"] = bool(out["frac_fp64_mfma"] >= 0.5)
+    return out
+
+
+def fwd_errors(Xg, Xo, cols):
+    """Relative forward errors on sampled columns: all entries, and the
+    strictly lower part alone (the entries the products compute; the
+    diagonal is 1 / L_ii on every path)."""
+    n = Xo.shape[0]
+    strict = np.arange(n)[:, None] > np.asarray(cols)[None, :]
+    return {"fwd_err_sampled_cols": float(np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)),
+            "fwd_err_strict": float(np.linalg.norm((Xg - Xo)[strict]) / np.linalg.norm(Xo[strict]))}
 
 
 def batched_secondary(P, torch, reps):
@@ -401,12 +442,14 @@ def main():
 
         Xo = oracle.tril_inverse_columns(L, cols)
         Xg = X[:, torch.from_numpy(cols).cuda()].cpu().numpy()
-        fwd = float(np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo))
+        fe = fwd_errors(Xg, Xo, cols)
         results[path] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12, "rel_residual": r["rel"],
-                         "fwd_err_sampled_cols": fwd, "profile": prof, "iterations": info.get("iterations"),
-                         "roofline": roofline(prof), "wall_s": wall}
+                         "rel_residual_in_loop": info.get("rel_residual"),
+                         "resid_error_est": info.get("resid_error_est"),
+                         "resid_error_bound": info.get("resid_error_bound"), **fe, "profile": prof,
+                         "iterations": info.get("iterations"), "roofline": roofline(prof), "wall_s": wall}
         log(f"path {path}: {ms:.3f} ms/step, {results[path]['tflops']:.2f} TFLOP/s, rel residual {r['rel']:.3e}, "
-            f"fwd err {fwd:.3e}")
+            f"fwd err {fe['fwd_err_sampled_cols']:.3e}, strictly lower {fe['fwd_err_strict']:.3e}")
         del X
         torch.cuda.empty_cache()
 
@@ -424,6 +467,7 @@ def main():
         "roofline": h["roofline"],
         "rel_residual": h["rel_residual"],
         "fwd_err_sampled_cols": h["fwd_err_sampled_cols"],
+        "fwd_err_strict": h["fwd_err_strict"],
         "paths": {k: {kk: vv for kk, vv in v.items() if kk != "profile"} for k, v in results.items()},
         "kernel_profile": {k: v["profile"] for k, v in results.items()},
         "paper_context": PAPER_CONTEXT,
@@ -431,8 +475,14 @@ def main():
     if "bf16_refine" in results and "f64" in results:
         out["speedup_vs_f64_path"] = round(results["f64"]["ms"] / results["bf16_refine"]["ms"], 3)
     if not args.no_secondary:
+        out["secondary"] = {}
+        log("plain FP64 n=256 leaf 32 and n=8192 leaf 64")
+        out["secondary"]["plain_n256"] = plain_config_secondary(P, torch, 256, 1, 32, 50)
+        out["secondary"]["plain_n8192"] = plain_config_secondary(P, torch, 8192, 2, 64, 5)
+        log(f"plain: {out['secondary']['plain_n256']['ms']} ms (n=256), "
+            f"{out['secondary']['plain_n8192']['ms']} ms (n=8192)")
         log("batched 4096 FP32 (graph replay)")
-        out["secondary"] = {"batched": batched_secondary(P, torch, 20)}
+        out["secondary"]["batched"] = batched_secondary(P, torch, 20)
         log(f"batched: {out['secondary']['batched']['ms']} ms")
         log("backward 64 x 1024 FP32")
         out["secondary"]["backward"] = backward_secondary(P, torch, 10)
