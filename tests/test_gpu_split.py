@@ -6,7 +6,7 @@ The split product forms N_L N_X from low-precision slices (hi + lo) of both
 factors with FP32 accumulation: its error per entry is at most 3 u^2
 (|N_L||N_X|)_ij from the slices (u = 2^-8 BF16, 2^-11 FP16) plus the FP32
 rounding of the sums (about sqrt(m) 2^-24 (|N_L||N_X|)_ij for m products per
-entry). The tests allow 16 u^2 + 4 sqrt(m) 2^-24 times |N_L||N_X| per entry
+entry). The tests allow 16 u^2 + 8 sqrt(m) 2^-24 times |N_L||N_X| per entry
 (plus the FP32 storage of R), and, over the whole matrix, twice the library's
 own estimate of the relative error (resid_error_est, whose constant is twice
 the one measured). Forward errors are checked through the exact identity
@@ -85,7 +85,7 @@ def test_split_residual_elementwise(P, mode, n, leaf):
         # FP64 rounding of both sides: the oracle's sums (gamma_n) and the
         # GPU's FP64 assembly of the diagonal terms, over |L||X|
         F = np.abs(np.tril(L)) @ np.abs(Xh)
-        tol = ((16 * u * u + 4 * np.sqrt(nsplit * n) * 2.0 ** -24) * A + 2.0 ** -23 * np.abs(Ro)
+        tol = ((16 * u * u + 8 * np.sqrt(nsplit * n) * 2.0 ** -24) * A + 2.0 ** -23 * np.abs(Ro)
                + (n + 8) * 2.0 ** -53 * F + 1e-300)
         low = np.tril_indices(n)
         d = np.abs(Rg - Ro)
