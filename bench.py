@@ -398,11 +398,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--seed", type=int, default=5)
-    ap.add_argument("--paths", default="bf16_refine,f16_refine,f64")
+    ap.add_argument("--paths", default="bf16_refine,f16_refine,f64", help="comma list, or none")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the batched and backward measurements")
+                    help="skip the secondary measurements")
+    ap.add_argument("--secondary", default="all",
+                    help="comma list of secondary measurements to run (plain, batched, backward, factored, "
+                         "skul, sqr, brsi, combrit) or 'all'")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain copy kernel of this size (counter calibration) and exit")
     args = ap.parse_args()
@@ -428,7 +431,7 @@ def main():
     torch.cuda.synchronize()
     flops = n ** 3 / 3.0
     results = {}
-    for path in [p for p in args.paths.split(",") if p]:
+    for path in [p for p in args.paths.split(",") if p and p != "none"]:
         leaf = 128 if n >= 4096 else 64
         log(f"path {path}: warmup {args.warmup}, steps {args.steps}")
         try:
@@ -453,8 +456,9 @@ def main():
         del X
         torch.cuda.empty_cache()
 
-    head = "bf16_refine" if "bf16_refine" in results else "f64"
-    h = results[head]
+    head = "bf16_refine" if "bf16_refine" in results else ("f64" if "f64" in results else None)
+    h = results[head] if head else {"tflops": 0.0, "ms": 0.0, "roofline": None, "rel_residual": None,
+                                    "fwd_err_sampled_cols": None, "fwd_err_strict": None}
     out = {
         "metric": METRIC, "value": round(h["tflops"], 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(h["ms"], 4), "higher_is_better": True, "scaling": "weak",
@@ -475,31 +479,40 @@ def main():
     if "bf16_refine" in results and "f64" in results:
         out["speedup_vs_f64_path"] = round(results["f64"]["ms"] / results["bf16_refine"]["ms"], 3)
     if not args.no_secondary:
+        want = set(args.secondary.split(",")) if args.secondary != "all" else None
+        run = lambda name: want is None or name in want  # noqa: E731
         out["secondary"] = {}
-        log("plain FP64 n=256 leaf 32 and n=8192 leaf 64")
-        out["secondary"]["plain_n256"] = plain_config_secondary(P, torch, 256, 1, 32, 50)
-        out["secondary"]["plain_n8192"] = plain_config_secondary(P, torch, 8192, 2, 64, 5)
-        log(f"plain: {out['secondary']['plain_n256']['ms']} ms (n=256), "
-            f"{out['secondary']['plain_n8192']['ms']} ms (n=8192)")
-        log("batched 4096 FP32 (graph replay)")
-        out["secondary"]["batched"] = batched_secondary(P, torch, 20)
-        log(f"batched: {out['secondary']['batched']['ms']} ms")
-        log("backward 64 x 1024 FP32")
-        out["secondary"]["backward"] = backward_secondary(P, torch, 10)
-        log(f"backward: {out['secondary']['backward']['backward_ms']} ms")
-        log("factored inverse n=4096 FP64")
-        out["secondary"]["factored"] = factored_secondary(P, torch, 5)
-        log(f"factored: {out['secondary']['factored']}")
-        log("SKUL n=4096 FP64")
-        out["secondary"]["skul"] = skul_secondary(P, torch, 3)
-        log(f"skul: {out['secondary']['skul']}")
-        log("SQR n=4096 FP64")
-        out["secondary"]["sqr"] = sqr_secondary(P, torch, 3)
-        log(f"sqr: {out['secondary']['sqr']}")
-        log("BRSI n=4096 FP64")
-        out["secondary"]["brsi"] = brsi_secondary(P, torch, 3)
-        log(f"brsi: {out['secondary']['brsi']}")
-        if n == 16384:
+        if run("plain"):
+            log("plain FP64 n=256 leaf 32 and n=8192 leaf 64")
+            out["secondary"]["plain_n256"] = plain_config_secondary(P, torch, 256, 1, 32, 50)
+            out["secondary"]["plain_n8192"] = plain_config_secondary(P, torch, 8192, 2, 64, 5)
+            log(f"plain: {out['secondary']['plain_n256']['ms']} ms (n=256), "
+                f"{out['secondary']['plain_n8192']['ms']} ms (n=8192)")
+        if run("batched"):
+            log("batched 4096 FP32 (graph replay)")
+            out["secondary"]["batched"] = batched_secondary(P, torch, 20)
+            log(f"batched: {out['secondary']['batched']['ms']} ms")
+        if run("backward"):
+            log("backward 64 x 1024 FP32")
+            out["secondary"]["backward"] = backward_secondary(P, torch, 10)
+            log(f"backward: {out['secondary']['backward']['backward_ms']} ms")
+        if run("factored"):
+            log("factored inverse n=4096 FP64")
+            out["secondary"]["factored"] = factored_secondary(P, torch, 5)
+            log(f"factored: {out['secondary']['factored']}")
+        if run("skul"):
+            log("SKUL n=4096 FP64")
+            out["secondary"]["skul"] = skul_secondary(P, torch, 3)
+            log(f"skul: {out['secondary']['skul']}")
+        if run("sqr"):
+            log("SQR n=4096 FP64")
+            out["secondary"]["sqr"] = sqr_secondary(P, torch, 3)
+            log(f"sqr: {out['secondary']['sqr']}")
+        if run("brsi"):
+            log("BRSI n=4096 FP64")
+            out["secondary"]["brsi"] = brsi_secondary(P, torch, 3)
+            log(f"brsi: {out['secondary']['brsi']}")
+        if n == 16384 and run("combrit"):
             log("COMBRIT beta = 4, 8 (FP64)")
             out["secondary"]["combrit"] = combrit_secondary(P, torch, Ld, 3)
             log(f"combrit: {out['secondary']['combrit']}")

@@ -193,7 +193,8 @@ size_t trinv_batched_workspace_bytes(int mode, int64_t batch, const int32_t *n_h
  * of uneven order, packed back to back. Independent diagonal blocks can be
  * inverted concurrently (Section 4.1, algorithm COMBRIT and its complexity
  * remark); each matrix runs the same recursion as trinv_tril_inverse (leaves
- * of 16 by the column recurrence of Section 4.2, then the 2 x 2 block levels).
+ * of 32 or 64 by the column recurrence of Section 4.2, then the 2 x 2 block
+ * levels).
  * mode: TRINV_F32 or TRINV_F64.
  *   n_host / n_dev: the orders n_i (host copy for validation, device copy read
  *     by the kernels; identical contents), 1 <= n_i <= 1024, batch < 2^31.
@@ -206,7 +207,7 @@ size_t trinv_batched_workspace_bytes(int mode, int64_t batch, const int32_t *n_h
  *     of the first zero diagonal of matrix i (X_i then holds non-finite
  *     values), or -1 if n_dev[i] is outside [1, 1024], or -2 if X_i holds a
  *     NaN or an infinity (a non-finite input entry, or overflow).
- *   opts: leaf 0 or 16 (else TRINV_ERR_ARG); unit_diag honoured; upper is
+ *   opts: leaf 0 (tuned or default), 32 or 64 (else TRINV_ERR_ARG); unit_diag honoured; upper is
  *     TRINV_ERR_UNSUPPORTED; blocking: wait and return TRINV_ERR_SINGULAR if
  *     any matrix is singular, else TRINV_ERR_NONFINITE if any status is -2.
  *   ws: at least trinv_batched_workspace_bytes bytes, caller-owned.
@@ -243,27 +244,28 @@ int trinv_tril_inverse_batched_noalloc(int mode, int64_t batch, const int32_t *n
 
 /* A configuration of the persistent batched launch. */
 typedef struct {
-  int32_t wg_tile_from; /* block order from which the level products use 128 x 128
-                           workgroup tiles (smaller blocks: 32 x 32 wave tiles);
-                           1024 = never. 0 = not applicable (level path). */
-  int32_t wgs_per_cu;   /* resident workgroups per CU (0 = not applicable) */
+  int32_t leaf;         /* leaf order, the recursion's cut-off: 32 or 64 (the
+                           diagonal blocks inverted by the column recurrence
+                           before the 2 x 2 levels) */
+  int32_t wgs_per_cu;   /* resident workgroups per CU (0 = the occupancy limit;
+                           0 in autotune output of the level path) */
   float ms;             /* time of one launch pair with it; -1 if not timed */
 } trinv_batched_config;
 
 /*
  * Autotuner of trinv_tril_inverse_batched (not in the paper): times the
- * persistent launch with every candidate configuration (wg_tile_from in
- * {128, 256, 1024}; wgs_per_cu from 1 up to the occupancy limit in powers of
- * two, and that limit) on the caller's buffers and stream, one untimed launch
- * and the fastest of three each, and keeps the fastest for this batch's order
- * signature (mode, count, sum of n_i, sum of n_i^2, largest n_i) for the rest
- * of the process: later trinv_tril_inverse_batched calls with the same
- * signature use it (the default is 128 and the occupancy limit). Arguments and
- * errors as trinv_tril_inverse_batched. On return X_packed and status_dev hold
- * the result of the chosen configuration; `out` (nullable) receives it.
- * Uniform batches that take the level path have nothing to tune (out->ms =
- * -1). Synchronises `stream` (not for graph capture: tune first, then
- * capture).
+ * persistent launch with every candidate configuration (leaf in {32, 64},
+ * or opts->leaf if set; wgs_per_cu from 1 up to the occupancy limit in powers
+ * of two, and that limit) on the caller's buffers and stream, one untimed
+ * launch and the fastest of three each, and keeps the fastest for this
+ * batch's order signature (mode, count, sum of n_i, sum of n_i^2, largest n_i)
+ * for the rest of the process: later trinv_tril_inverse_batched calls with
+ * the same signature use it (the default is leaf 64 for FP32, 32 for FP64,
+ * and the occupancy limit). Arguments and errors as
+ * trinv_tril_inverse_batched. On return X_packed and status_dev hold the
+ * result of the chosen configuration; `out` (nullable) receives it. Uniform
+ * batches that take the level path have nothing to tune (out->ms = -1).
+ * Synchronises `stream` (not for graph capture: tune first, then capture).
  */
 int trinv_batched_autotune(int mode, int64_t batch, const int32_t *n_host, const int32_t *n_dev,
                            const int64_t *off_host, const int64_t *off_dev, const void *L_packed,
@@ -272,8 +274,8 @@ int trinv_batched_autotune(int mode, int64_t batch, const int32_t *n_host, const
 
 /* Sets the configuration later trinv_tril_inverse_batched calls use for
  * batches with this order signature (as trinv_batched_autotune would), e.g.
- * one an earlier process found. cfg->wg_tile_from >= 128, cfg->wgs_per_cu >= 0
- * (0 or above the occupancy limit: that limit); else TRINV_ERR_ARG. */
+ * one an earlier process found. cfg->leaf 32 or 64, cfg->wgs_per_cu >= 0 (0
+ * or above the occupancy limit: that limit); else TRINV_ERR_ARG. */
 int trinv_batched_set_config(int mode, int64_t batch, const int32_t *n_host, const trinv_batched_config *cfg);
 
 /*

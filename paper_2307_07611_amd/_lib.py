@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
 
 
 class BatchedConfig(ctypes.Structure):
-    _fields_ = [("wg_tile_from", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("ms", ctypes.c_float)]
+    _fields_ = [("leaf", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 class Info(ctypes.Structure):

@@ -211,7 +211,7 @@ def batched_autotune(L_packed: torch.Tensor, sizes, offsets=None, mode=None, *, 
                      n_dev=None, off_dev=None, status=None) -> dict:
     """Times the persistent batched launch's configurations on this batch and
     keeps the fastest for batches with the same orders (trinv_batched_autotune);
-    returns it as a dict (wg_tile_from, wgs_per_cu, ms). X (``out``) and
+    returns it as a dict (leaf, wgs_per_cu, ms). X (``out``) and
     ``status`` hold the result of the chosen configuration."""
     _check_dev(L_packed)
     import numpy as np
@@ -242,16 +242,16 @@ def batched_autotune(L_packed: torch.Tensor, sizes, offsets=None, mode=None, *, 
                                     ctypes.byref(o), ws.data_ptr(), ws.numel(), _stream(), ctypes.byref(cfg))
     if st != _lib.OK:
         raise _lib.TrinvError(st, "trinv_batched_autotune")
-    return {"wg_tile_from": cfg.wg_tile_from, "wgs_per_cu": cfg.wgs_per_cu, "ms": cfg.ms}
+    return {"leaf": cfg.leaf, "wgs_per_cu": cfg.wgs_per_cu, "ms": cfg.ms}
 
 
-def batched_set_config(sizes, mode, wg_tile_from, wgs_per_cu=0):
+def batched_set_config(sizes, mode, leaf, wgs_per_cu=0):
     """Pin the persistent batched launch's configuration for batches with these
     orders (trinv_batched_set_config)."""
     import numpy as np
 
     sizes_np = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
-    cfg = _lib.BatchedConfig(wg_tile_from, wgs_per_cu, -1.0)
+    cfg = _lib.BatchedConfig(leaf, wgs_per_cu, -1.0)
     st = _lib.load().trinv_batched_set_config(_lib.MODES[mode], len(sizes_np), sizes_np.ctypes.data,
                                               ctypes.byref(cfg))
     if st != _lib.OK:

@@ -54,14 +54,17 @@ WsLevels carve_levels(Carve& c, int mode, int64_t batch, int64_t n, int64_t leaf
 
 int64_t level_leaf(int mode, int64_t n, int32_t opt_leaf) { return opt_leaf ? opt_leaf : default_leaf(mode, n); }
 
-// Tunable parameters of the persistent launch: the block order from which
-// level products use 128 x 128 workgroup tiles (below it: 32 x 32 wave
-// tiles; 1024 never for orders <= 1024) and the resident workgroups per CU
-// (0: the occupancy limit).
+// Tunable parameters of the persistent launch: the leaf order (the
+// recursion's cut-off: 32 or 64; 0 = the mode's default) and the resident
+// workgroups per CU (0: the occupancy limit).
 struct PersistentConfig {
-  int wg_from = 128;
+  int leaf = 0;
   int per_cu = 0;
 };
+
+// Default leaf order: 64 for FP32; 32 for FP64 (a 64-leaf stage of FP64 L^T
+// takes 136 KB of LDS, one workgroup per CU).
+int default_batched_leaf(int mode) { return mode == TRINV_F32 ? 64 : 32; }
 
 // The kernel's work depends on the orders only: a batch is keyed by its mode,
 // count, sum of orders, sum of squared orders and largest order.
@@ -85,7 +88,7 @@ int check_batch(int mode, int64_t batch, const int32_t* n_host, const int32_t* n
   if (!n_host || !off_host || !n_dev || !off_dev || !L_packed || !X_packed || !status_dev) return TRINV_ERR_ARG;
   if (mode != TRINV_F64 && mode != TRINV_F32) return TRINV_ERR_UNSUPPORTED;
   if (o.upper) return TRINV_ERR_UNSUPPORTED;
-  if (o.leaf != 0 && o.leaf != 16) return TRINV_ERR_ARG;
+  if (o.leaf != 0 && o.leaf != 32 && o.leaf != 64) return TRINV_ERR_ARG;
   const size_t es = mode == TRINV_F32 ? 4 : 8;
   int64_t extent = 0, s1 = 0, s2 = 0;
   int nmax = 0;
@@ -106,15 +109,17 @@ int check_batch(int mode, int64_t batch, const int32_t* n_host, const int32_t* n
   return TRINV_OK;
 }
 
-// The persistent launch pair with configuration c.
+// The persistent launch pair with configuration c (opts.leaf, when set,
+// overrides the configuration's leaf).
 hipError_t launch_persistent(int mode, int64_t batch, const int32_t* n_dev, const int64_t* off_dev,
                              const void* L_packed, void* X_packed, int32_t* status_dev, const WsPersistent& w,
-                             int unit, const PersistentConfig& c, hipStream_t s) {
+                             const trinv_opts& o, const PersistentConfig& c, hipStream_t s) {
+  const int leaf = o.leaf ? o.leaf : (c.leaf ? c.leaf : default_batched_leaf(mode));
   if (mode == TRINV_F32)
     return launch_batched<float>(batch, n_dev, off_dev, (const float*)L_packed, (float*)X_packed, status_dev,
-                                 w.order, w.queue, unit, batched_grid<float>(batch, c.per_cu), c.wg_from, s);
+                                 w.order, w.queue, o.unit_diag, batched_grid<float>(batch, leaf, c.per_cu), leaf, s);
   return launch_batched<double>(batch, n_dev, off_dev, (const double*)L_packed, (double*)X_packed, status_dev,
-                                w.order, w.queue, unit, batched_grid<double>(batch, c.per_cu), c.wg_from, s);
+                                w.order, w.queue, o.unit_diag, batched_grid<double>(batch, leaf, c.per_cu), leaf, s);
 }
 
 }  // namespace
@@ -128,7 +133,7 @@ extern "C" size_t trinv_batched_workspace_bytes(int mode, int64_t batch, const i
     bool same = n_host[0] >= 128 && n_host[0] <= 1024;
     for (int64_t i = 1; i < batch && same; ++i) same = n_host[i] == n_host[0];
     const trinv_opts o = resolve_opts(opts);
-    if (same && (o.leaf == 0 || o.leaf == 16))
+    if (same && (o.leaf == 0 || o.leaf == 32 || o.leaf == 64))
       carve_levels(c, mode, batch, n_host[0], level_leaf(mode, n_host[0], o.leaf));
   }
   return c.used;
@@ -173,8 +178,8 @@ extern "C" int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t
       HIP_TRY(launch_nonfinite_status<float>((const float*)X_packed, n, n * n, batch, status_dev, s));
   } else {
     ProfLaunch pl(mode == TRINV_F32 ? "f32_batched" : "f64_batched", flops, bytes, s);
-    HIP_TRY(launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o.unit_diag,
-                              tuned_config(key), s));
+    HIP_TRY(launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o, tuned_config(key),
+                              s));
   }
   if (!o.blocking) return TRINV_OK;
   std::vector<int32_t> st((size_t)batch);
@@ -207,11 +212,13 @@ extern "C" int trinv_batched_autotune(int mode, int64_t batch, const int32_t* n_
   if (!ws || !c.ok()) return TRINV_ERR_WORKSPACE;
   if (level_path(batch, n_host, off_host)) return TRINV_OK;  // the level path has nothing to tune
   hipStream_t s = (hipStream_t)stream;
-  const int occ = mode == TRINV_F32 ? batched_occupancy<float>(nullptr) : batched_occupancy<double>(nullptr);
-  std::vector<int> per_cu = {1};
-  for (int k = 2; k <= occ; k *= 2) per_cu.push_back(k);
-  if (per_cu.back() != occ) per_cu.push_back(occ);
-  const int wg_from[] = {128, 256, 1024};
+  std::vector<PersistentConfig> cands;
+  for (int leaf : {32, 64}) {
+    if (o.leaf && leaf != o.leaf) continue;
+    const int occ = mode == TRINV_F32 ? batched_occupancy<float>(leaf, nullptr) : batched_occupancy<double>(leaf, nullptr);
+    for (int k = 1; k <= occ; k *= 2) cands.push_back(PersistentConfig{leaf, k});
+    if ((occ & (occ - 1)) != 0) cands.push_back(PersistentConfig{leaf, occ});
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -221,30 +228,26 @@ extern "C" int trinv_batched_autotune(int mode, int64_t batch, const int32_t* n_
   PersistentConfig best;
   float best_ms = -1.0f;
   hipError_t err = hipSuccess;
-  for (int wf : wg_from) {
-    for (int pc : per_cu) {
-      const PersistentConfig cfg{wf, pc};
-      // one untimed launch, then the fastest of three
-      err = launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o.unit_diag, cfg, s);
-      float ms = -1.0f;
-      for (int r = 0; r < 3 && err == hipSuccess; ++r) {
-        if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
-        if ((err = launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o.unit_diag, cfg,
-                                     s)) != hipSuccess)
-          break;
-        if ((err = hipEventRecord(e1, s)) != hipSuccess) break;
-        if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
-        float t = 0.0f;
-        if ((err = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) break;
-        if (ms < 0.0f || t < ms) ms = t;
-      }
-      if (err != hipSuccess) break;
-      if (best_ms < 0.0f || ms < best_ms) {
-        best_ms = ms;
-        best = cfg;
-      }
+  for (const PersistentConfig& cfg : cands) {
+    // one untimed launch, then the fastest of three
+    err = launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o, cfg, s);
+    float ms = -1.0f;
+    for (int r = 0; r < 3 && err == hipSuccess; ++r) {
+      if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
+      if ((err = launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o, cfg, s)) !=
+          hipSuccess)
+        break;
+      if ((err = hipEventRecord(e1, s)) != hipSuccess) break;
+      if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+      float t = 0.0f;
+      if ((err = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) break;
+      if (ms < 0.0f || t < ms) ms = t;
     }
     if (err != hipSuccess) break;
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = cfg;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -254,9 +257,9 @@ extern "C" int trinv_batched_autotune(int mode, int64_t batch, const int32_t* n_
     g_tuned[key] = best;
   }
   // leave X and status from the chosen configuration
-  HIP_TRY(launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o.unit_diag, best, s));
+  HIP_TRY(launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o, best, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (out) *out = trinv_batched_config{best.wg_from, best.per_cu, best_ms};
+  if (out) *out = trinv_batched_config{best.leaf, best.per_cu, best_ms};
   return TRINV_OK;
 }
 
@@ -264,7 +267,7 @@ extern "C" int trinv_batched_set_config(int mode, int64_t batch, const int32_t* 
                                         const trinv_batched_config* cfg) {
   if (batch <= 0 || batch > INT32_MAX || !n_host || !cfg) return TRINV_ERR_ARG;
   if (mode != TRINV_F64 && mode != TRINV_F32) return TRINV_ERR_UNSUPPORTED;
-  if (cfg->wg_tile_from < 128 || cfg->wgs_per_cu < 0) return TRINV_ERR_ARG;
+  if ((cfg->leaf != 32 && cfg->leaf != 64) || cfg->wgs_per_cu < 0) return TRINV_ERR_ARG;
   int64_t s1 = 0, s2 = 0;
   int nmax = 0;
   for (int64_t i = 0; i < batch; ++i) {
@@ -275,7 +278,7 @@ extern "C" int trinv_batched_set_config(int mode, int64_t batch, const int32_t* 
     nmax = std::max<int>(nmax, (int)n);
   }
   std::lock_guard<std::mutex> lock(g_tuned_mu);
-  g_tuned[BatchKey(mode, batch, s1, s2, nmax)] = PersistentConfig{cfg->wg_tile_from, cfg->wgs_per_cu};
+  g_tuned[BatchKey(mode, batch, s1, s2, nmax)] = PersistentConfig{cfg->leaf, cfg->wgs_per_cu};
   return TRINV_OK;
 }
 
@@ -298,8 +301,7 @@ extern "C" int trinv_tril_inverse_batched_noalloc(int mode, int64_t batch, const
   WsPersistent w{};
   HIP_TRY(batched_scratch(&w.order, &w.queue));
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o.unit_diag,
-                            tuned_config(key), s));
+  HIP_TRY(launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o, tuned_config(key), s));
   if (!o.blocking) return TRINV_OK;
   // statuses in fixed-size pieces (no host allocation either)
   int32_t st[1024];

@@ -173,14 +173,14 @@ hipError_t launch_nonfinite_status(const T* X, int64_t n, int64_t stride, int64_
 
 // Uneven batch in one persistent launch (persistent.hip): a plan kernel sorts
 // the matrices by order into `order` (batch entries) and resets `queue`, then
-// `grid` workgroups invert whole matrices taken from the queue (leaves of 16;
-// levels whose blocks have order >= wg_from use 128 x 128 workgroup tiles,
-// smaller ones 32 x 32 wave tiles; wg_from >= 128).
+// `grid` workgroups invert whole matrices taken from the queue (leaves of
+// order `leaf`, 32 or 64, by the column recurrence; then the 2 x 2 levels on
+// MFMA tiles).
 // status[i]: 0, the 1-based index of the first zero diagonal, -1 for an
 // order outside [1, 1024], or -2 if a NaN or an infinity was stored into X_i.
 template <typename T>
 hipError_t launch_batched(int64_t batch, const int32_t* n_dev, const int64_t* off_dev, const T* L, T* X,
-                          int32_t* status, int32_t* order, uint32_t* queue, int unit, int grid, int wg_from,
+                          int32_t* status, int32_t* order, uint32_t* queue, int unit, int grid, int leaf,
                           hipStream_t s);
 // Device scratch of the allocation-free batched entry point (a file-scope
 // device array, one copy per device): room for the plan of kNoAllocMaxBatch
@@ -189,13 +189,13 @@ hipError_t launch_batched(int64_t batch, const int32_t* n_dev, const int64_t* of
 constexpr int64_t kNoAllocMaxBatch = 65536;
 constexpr int kMaxDevices = 64;
 hipError_t batched_scratch(int32_t** order, uint32_t** queue);
-// Resident workgroups of the persistent kernel per CU (occupancy) and, in
-// *cus, the device's CU count.
+// Resident workgroups of the persistent kernel (leaf order 32 or 64) per CU
+// (occupancy) and, in *cus, the device's CU count.
 template <typename T>
-int batched_occupancy(int* cus);
+int batched_occupancy(int leaf, int* cus);
 // Persistent grid size: per_cu workgroups per CU (the occupancy if per_cu is
 // 0 or above it), at most batch.
 template <typename T>
-int batched_grid(int64_t batch, int per_cu);
+int batched_grid(int64_t batch, int leaf, int per_cu);
 
 }  // namespace trinv

@@ -183,7 +183,7 @@ def test_batched_argument_errors_before_any_launch(lib):
     assert call(_lib.F32, 3, n, off, 1 << 30, 1 << 31, 1 << 32, up) == _lib.ERR_UNSUPPORTED
     lf = _lib.Opts()
     lib.trinv_default_opts(ctypes.byref(lf))
-    for leaf in (32, 64):  # uneven orders take leaf 0 or 16
+    for leaf in (16, 128):  # the persistent launch takes leaf 0, 32 or 64
         lf.leaf = leaf
         assert call(_lib.F32, 3, n, off, 1 << 30, 1 << 31, 1 << 32, lf) == _lib.ERR_ARG
     # too small a workspace
@@ -269,10 +269,10 @@ def test_batched_tuner_argument_errors(lib):
     checks its fields (no launch in either)."""
     from paper_2307_07611_amd import _lib
 
-    cfg = _lib.BatchedConfig(128, 0, -1.0)
+    cfg = _lib.BatchedConfig(64, 0, -1.0)
     sizes = np.array([16, 300, 1024], dtype=np.int32)
     assert lib.trinv_batched_set_config(_lib.F32, 3, sizes.ctypes.data, ctypes.byref(cfg)) == _lib.OK
-    bad = _lib.BatchedConfig(64, 0, -1.0)
+    bad = _lib.BatchedConfig(16, 0, -1.0)
     assert lib.trinv_batched_set_config(_lib.F32, 3, sizes.ctypes.data, ctypes.byref(bad)) == _lib.ERR_ARG
     assert lib.trinv_batched_set_config(_lib.F32, 3, None, ctypes.byref(cfg)) == _lib.ERR_ARG
     assert lib.trinv_batched_set_config(_lib.BF16_REFINE, 3, sizes.ctypes.data, ctypes.byref(cfg)) == \

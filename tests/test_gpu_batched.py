@@ -78,7 +78,7 @@ EDGE_SIZES = [1, 2, 3, 15, 16, 17, 31, 32, 33, 47, 63, 64, 65, 96, 127, 128, 129
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-@pytest.mark.parametrize("leaf", [0, 16])
+@pytest.mark.parametrize("leaf", [0, 32, 64])
 def test_uneven_batch_vs_oracle(P, dt, leaf):
     import torch
 
@@ -216,19 +216,18 @@ def test_uniform_batches(P, dt, n, batch):
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-@pytest.mark.parametrize("wg_from,per_cu", [(128, 1), (256, 2), (1024, 0), (512, 1), (256, 64)])
-def test_pinned_configurations_vs_oracle(P, dt, wg_from, per_cu):
-    """Every configuration the autotuner may choose (and 512) gives a correct
-    inverse of every matrix: the level products switch between 128 x 128
-    workgroup tiles and 32 x 32 wave tiles at wg_from; a workgroup count per
-    CU above the occupancy limit runs at that limit."""
+@pytest.mark.parametrize("leaf,per_cu", [(32, 1), (64, 1), (32, 2), (64, 2), (64, 0), (32, 64)])
+def test_pinned_configurations_vs_oracle(P, dt, leaf, per_cu):
+    """Every configuration the autotuner may choose gives a correct inverse of
+    every matrix: leaves of 32 or 64 (the recursion's cut-off); a workgroup
+    count per CU above the occupancy limit runs at that limit."""
     import torch
 
-    banner(f"batched {dt} pinned wg_tile_from={wg_from} wgs_per_cu={per_cu}")
+    banner(f"batched {dt} pinned leaf={leaf} wgs_per_cu={per_cu}")
     sizes = np.array(EDGE_SIZES, dtype=np.int32)
     np_dt = np.float32 if dt == "f32" else np.float64
     packed, offs, mats = make_batch(sizes, np_dt, seed0=5000)
-    P.batched_set_config(sizes, dt, wg_from, per_cu)
+    P.batched_set_config(sizes, dt, leaf, per_cu)
     L = torch.from_numpy(packed).cuda()
     X, status = P.tril_inverse_batched(L, sizes, offs, dt)
     torch.cuda.synchronize()
@@ -249,7 +248,7 @@ def test_autotune_then_graph_vs_oracle(P):
     g.L.copy_(torch.from_numpy(packed).cuda())
     cfg = g.tune()
     print(f"autotune: {cfg}", flush=True)
-    assert cfg["wg_tile_from"] in (128, 256, 1024) and cfg["wgs_per_cu"] >= 1 and cfg["ms"] > 0
+    assert cfg["leaf"] in (32, 64) and cfg["wgs_per_cu"] >= 1 and cfg["ms"] > 0
     check(mats, unpack(g.X.cpu().numpy(), offs, sizes), TOL["f32"], oracle_every=25)
     g.X.zero_()
     g.capture(tune=False)
@@ -273,7 +272,7 @@ def test_autotune_f64_uneven(P):
     cfg = P.batched_autotune(L, sizes, offs, "f64", out=X, status=status)
     torch.cuda.synchronize()
     print(f"autotune: {cfg}", flush=True)
-    assert cfg["wg_tile_from"] in (128, 256, 1024) and cfg["wgs_per_cu"] >= 1 and cfg["ms"] > 0
+    assert cfg["leaf"] in (32, 64) and cfg["wgs_per_cu"] >= 1 and cfg["ms"] > 0
     assert int(status.abs().sum()) == 0
     check(mats, unpack(X.cpu().numpy(), offs, sizes), TOL["f64"], oracle_every=5)
     X2, st2 = P.tril_inverse_batched(L, sizes, offs, "f64")
