@@ -7,10 +7,10 @@
 // v_mfma_f32_32x32x16_{bf16,f16}; each wave owns a 128 x 128 sub-tile
 // (4 x 4 blocks of 32 x 32, 256 FP32 accumulators per lane). Both operands
 // are k-contiguous in memory (B is stored transposed), so a K step is staged
-// by direct global -> LDS 16-byte loads into a ring of LDS stages (at most
-// 160 KB: five stages of K = 32 for one product, three for the 2-product form,
-// two for the 3-product form), issued one stage short of the ring ahead, and
-// every MFMA operand is one 16-byte LDS read. Lane
+// by direct global -> LDS 16-byte loads into a ring of five LDS stages (at
+// most 160 KB: K = 32 per stage for one product, K = 16 for the 2- and
+// 3-product forms), issued one stage short of the ring ahead, and every MFMA
+// operand is one 16-byte LDS read. Lane
 // layouts (measured on gfx950): lane l supplies A(l%32, 8(l/32)+e) and
 // B(8(l/32)+e, l%32), e = 0..7, and receives D(8(r/4) + 4(l/32) + r%4, l%32)
 // in register r.
@@ -35,18 +35,28 @@ namespace {
 constexpr int LT = 256;  // workgroup tile (rows and columns)
 constexpr int kTrLd = LT + 8;  // row length of a transposed tile staged in LDS (16-byte rows, fewer bank conflicts)
 
-template <int NSPLIT>
+// K per LDS stage: 16 (one MFMA k step) for the 2- and 3-product forms on
+// panel-blocked planes, whose stages are large (three or four staged tiles),
+// so that five stages fit and loads run four stages ahead; 32 otherwise.
+constexpr int lp_kt(int nsplit, int klo) { return (klo == kLoN0Pb && nsplit >= 2) ? 16 : 32; }
+
+template <int NSPLIT, int KT_>
 struct LpShape {
-  static constexpr int KT = 32;  // K per LDS stage (two MFMA k steps)
+  static constexpr int KT = KT_;
   static constexpr int NT = NSPLIT == 1 ? 2 : (NSPLIT == 2 ? 3 : 4);  // staged tiles per stage
-  // LDS stages (at most 160 KB): loads run NBUF - 1 stages ahead
-  static constexpr int NBUF = 163840 / (NT * 256 * KT * 2) < 5 ? 163840 / (NT * 256 * KT * 2) : 5;
-  static_assert(NBUF >= 2, "two stages at least");
   static constexpr int CPR = KT / 8;                // 16-byte chunks per tile row
   static constexpr int TILE = LT * KT;              // elements of one staged tile (no padding)
   static constexpr int RPI = 512 / KT;              // tile rows per 1 KB direct-load instruction
   static constexpr int IPW = KT / 8;                // direct-load instructions per wave per tile
+  static constexpr int LPS = NT * IPW;              // direct loads per thread and stage
   static constexpr int RSW = 128 / KT;              // rows per swizzle step
+  // LDS stages (at most 160 KB, at most 5, and at most 63 loads of newer
+  // stages outstanding per thread): loads run NBUF - 1 stages ahead
+  static constexpr int NB_LDS = 163840 / (NT * LT * KT * 2);
+  static constexpr int NB_VM = 1 + 63 / LPS;
+  static constexpr int NBUF = NB_LDS < NB_VM ? (NB_LDS < 5 ? NB_LDS : 5) : (NB_VM < 5 ? NB_VM : 5);
+  static_assert(NBUF >= 2, "two stages at least");
+  static_assert(KT == 16 || KT == 32, "one or two MFMA k steps per stage");
   // Chunk position p of row r holds the row's k-chunk p ^ swz(r): 16
   // consecutive rows read at one logical chunk hit 16 distinct bank groups.
   static __device__ __forceinline__ int swz(int r) { return (r / RSW) % CPR; }
@@ -139,7 +149,7 @@ int64_t gemm_lp_tiles(const GemmBatch& bt, int tiles) {
 
 template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
 __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
-  typedef LpShape<NSPLIT> S;
+  typedef LpShape<NSPLIT, lp_kt(NSPLIT, KLO)> S;
   constexpr int KT = S::KT;
   // NBUF stages x NT tiles x TILE elements (all of the CU's LDS); after the
   // main loop its first bytes hold the per-wave partial sums of the residual
@@ -225,19 +235,21 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
       }
     }
   }
-  auto issue = [&](int buf, int64_t kstage) {  // loads of the stage starting at klo + kstage
+  // direct load i of tile tt of the stage starting at klo + kstage, into buffer buf
+  auto issue_one = [&](int buf, int64_t kstage, int tt, int i) __attribute__((always_inline)) {
     typedef __attribute__((address_space(3))) char lds_char;
     lds_char* base = (lds_char*)lds + (size_t)buf * S::NT * S::TILE * 2;
+    const char* src = (const char*)tb[tt] + (PB ? (kstage >> 4) * 4096 * 2 : kstage * 2);
+    __builtin_amdgcn_global_load_lds((const void*)(src + off[tt][i]),
+                                     (__attribute__((address_space(3))) void*)(base + tt * S::TILE * 2 +
+                                                                               (wave * S::IPW + i) * 1024),
+                                     16, 0, 0);
+  };
+  auto issue = [&](int buf, int64_t kstage) {  // loads of the stage starting at klo + kstage
 #pragma unroll
-    for (int tt = 0; tt < S::NT; ++tt) {
-      const char* src = (const char*)tb[tt] + (PB ? (kstage >> 4) * 4096 * 2 : kstage * 2);
+    for (int tt = 0; tt < S::NT; ++tt)
 #pragma unroll
-      for (int i = 0; i < S::IPW; ++i)
-        __builtin_amdgcn_global_load_lds((const void*)(src + off[tt][i]),
-                                         (__attribute__((address_space(3))) void*)(base + tt * S::TILE * 2 +
-                                                                                   (wave * S::IPW + i) * 1024),
-                                         16, 0, 0);
-    }
+      for (int i = 0; i < S::IPW; ++i) issue_one(buf, kstage, tt, i);
   };
   // Fragment of tile tt for block blk at k step ks (16 wide): 8 elements of
   // one tile row, read from its swizzled chunk position.
@@ -299,41 +311,34 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  // Fragments of one stage: fr[ks][tile][block]. Products of a k step
-  // (A tile x B tile): A_hi B_hi (1); A_lo B_hi, A_hi B_hi (2);
-  // A_hi B_lo, A_lo B_hi, A_hi B_hi (3).
-  constexpr int KS = S::KT / 16, NT = S::NT;
-  static_assert(KS == 2, "two k steps per stage");
-  u32x4 fr[KS][NT][4];
+  // Fragments: fr[slot][tile][block], one slot per MFMA k step in flight
+  // (slot = k step within the stage when a stage holds two k steps, stage
+  // parity when it holds one). Products of a k step (A tile x B tile):
+  // A_hi B_hi (1); A_lo B_hi, A_hi B_hi (2); A_hi B_lo, A_lo B_hi, A_hi B_hi (3).
+  constexpr int KS = S::KT / 16, NT = S::NT, MF = 16 * NSPLIT;
+  u32x4 fr[2][NT][4];
   auto prod_a = [](int p) constexpr { return NSPLIT == 1 ? 0 : (NSPLIT == 2 ? (p == 0 ? 2 : 0) : (p == 1 ? 2 : 0)); };
   auto prod_b = [](int p) constexpr { return NSPLIT == 3 ? (p == 0 ? 3 : 1) : 1; };
-  auto read_tile = [&](const u16* base, auto KSI, auto TTI) __attribute__((always_inline)) {
-    constexpr int ks = decltype(KSI)::value, tt = decltype(TTI)::value;
+  auto read_tile = [&](const u16* base, auto FI, auto KSI, auto TTI) __attribute__((always_inline)) {
+    constexpr int f = decltype(FI)::value, ks = decltype(KSI)::value, tt = decltype(TTI)::value;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) fr[ks][tt][b] = frag(base, tt, 16 * ks, b);
+    for (int b = 0; b < 4; ++b) fr[f][tt][b] = frag(base, tt, 16 * ks, b);
   };
-  auto mma_prod = [&](auto KSI, auto PI) __attribute__((always_inline)) {
-    constexpr int ks = decltype(KSI)::value, p = decltype(PI)::value;
-    constexpr int ta = prod_a(p), tb_ = prod_b(p);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = mma<F16>(fr[ks][ta][i], fr[ks][tb_][j], acc[i][j]);
+  auto reads = [&](const u16* base, auto FI, auto KSI) __attribute__((always_inline)) {
+    static_for<0, NT>([&](auto T) { read_tile(base, FI, KSI, T); });
   };
-  using I0 = std::integral_constant<int, 0>;
-  using I1 = std::integral_constant<int, 1>;
-  // A stage is split around the barrier that makes the next stage readable:
-  // its "head" fragments (k step 0) are read before the stage starts, the
-  // rest (k step 1) while the head products run; after the barrier the next
-  // stage's head fragments are read while this stage's "tail" products (k
-  // step 1 only) run.
-  auto head_reads = [&](const u16* base) __attribute__((always_inline)) {
-    static_for<0, NT>([&](auto T) { read_tile(base, I0{}, T); });
+  // MFMAs [LO, HI) of a k step's MF = 16 NSPLIT (product-major, then i, j)
+  auto mmas = [&](auto FI, auto LOI, auto HII) __attribute__((always_inline)) {
+    constexpr int f = decltype(FI)::value;
+    static_for<decltype(LOI)::value, decltype(HII)::value>([&](auto MI) {
+      constexpr int m = decltype(MI)::value, p = m / 16, i = (m / 4) % 4, j = m % 4;
+      acc[i][j] = mma<F16>(fr[f][prod_a(p)][i], fr[f][prod_b(p)][j], acc[i][j]);
+    });
   };
-  auto rest_and_head_products = [&](const u16* base) __attribute__((always_inline)) {
-    static_for<0, NT>([&](auto T) { read_tile(base, I1{}, T); });
-    static_for<0, NSPLIT>([&](auto P) { mma_prod(I0{}, P); });
-    constexpr int RD = 4 * NT, MF = 16 * NSPLIT, Q = MF / RD, REM = MF - Q * RD;
+  // interleave the last NMF MFMAs issued with the 4 NT fragment reads issued
+  // beside them
+  auto interleave = [](auto NMFI) __attribute__((always_inline)) {
+    constexpr int RD = 4 * NT, NMF = decltype(NMFI)::value, Q = NMF / RD, REM = NMF - Q * RD;
 #pragma unroll
     for (int g = 0; g < RD; ++g) {
       __builtin_amdgcn_sched_group_barrier(0x008, Q, 0);  // MFMA
@@ -341,9 +346,10 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
     }
     if (REM) __builtin_amdgcn_sched_group_barrier(0x008, REM, 0);
   };
-  auto tail_products = [&]() __attribute__((always_inline)) {
-    static_for<0, NSPLIT>([&](auto P) { mma_prod(I1{}, P); });
-  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using IH = std::integral_constant<int, MF / 2>;
+  using IM = std::integral_constant<int, MF>;
 
   // NBUF-stage pipeline: stage st lives in buffer st % NBUF. The loads of
   // stages 0 .. NBUF - 1 are issued up front; stage st + NBUF is issued into
@@ -351,9 +357,24 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   // that makes stage st + 1 readable). Before that barrier each wave waits
   // until only its loads of the newer stages are outstanding.
   constexpr int NBUF = S::NBUF;
-  constexpr int LPS = S::NT * S::IPW;  // direct loads per thread and stage
+  constexpr int LPS = S::LPS;
   if (klo < khi) {
     const int nst = (int)((khi - klo + S::KT - 1) / S::KT);
+    // Stage order. The tiles of a block (panel-blocked products) share row
+    // and column panels but start K at their own diagonal offsets; so that
+    // the tiles sharing a panel read the same k at the same time (and the
+    // panel is fetched once into the XCD's L2), each tile first runs
+    // ascending from the block's common start s (n0 of its last tile
+    // column) to its own end, then descending from s to its own start:
+    // stage st covers K from klo + kpos(st).
+    int a_s = 0;
+    if constexpr (PB) {
+      const int64_t s0 = imin64(bj * GB + GB - 1, tn - 1) * LT;
+      a_s = s0 <= klo ? 0 : (int)imin64((s0 - klo) / S::KT, nst);
+    }
+    auto kpos = [&](int st) -> int64_t {
+      return (int64_t)S::KT * (st < nst - a_s ? a_s + st : nst - 1 - st);
+    };
     auto ready = [&](int st) __attribute__((always_inline)) {
       if (st + NBUF - 2 < nst)
         wait_barrier<(NBUF - 2) * LPS>();
@@ -361,7 +382,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
         wait_barrier<0>();
     };
     auto guard_mask = [&](int st) __attribute__((always_inline)) {
-      const int64_t k0 = klo + (int64_t)st * S::KT;
+      const int64_t k0 = klo + kpos(st);
       bool guard = (k0 + S::KT > K);
       if (AM != 0 && k0 + S::KT > m0 && k0 < m0 + LT) guard = true;
       if (BM != 0 && k0 + S::KT > n0 && k0 < n0 + LT) guard = true;
@@ -371,24 +392,92 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
       }
     };
     auto stage_base = [&](int st) { return lds + (st % NBUF) * (NT * S::TILE); };
+    // the barrier before stage st + 1: wait, refill the buffer of stage st,
+    // mask stage st + 1 if needed
+    auto next_stage = [&](int st) __attribute__((always_inline)) {
+      ready(st + 1);  // also: every wave has read stage st
+      if (st + NBUF < nst) issue(st % NBUF, kpos(st + NBUF));
+      guard_mask(st + 1);
+    };
+    if constexpr (KS == 2) {
 #pragma unroll
-    for (int p = 0; p < NBUF - 1; ++p)
-      if (p < nst) issue(p, (int64_t)p * S::KT);
-    ready(0);
-    if (NBUF - 1 < nst) issue(NBUF - 1, (int64_t)(NBUF - 1) * S::KT);
-    guard_mask(0);
-    head_reads(stage_base(0));
-    for (int st = 0; st < nst; ++st) {
-      rest_and_head_products(stage_base(st));
-      __builtin_amdgcn_sched_barrier(0);
-      if (st + 1 < nst) {
-        ready(st + 1);  // also: every wave has read stage st
-        if (st + NBUF < nst) issue(st % NBUF, (int64_t)(st + NBUF) * S::KT);
-        guard_mask(st + 1);
-        head_reads(stage_base(st + 1));
+      for (int p = 0; p < NBUF - 1; ++p)
+        if (p < nst) issue(p, kpos(p));
+      ready(0);
+      if (NBUF - 1 < nst) issue(NBUF - 1, kpos(NBUF - 1));
+      guard_mask(0);
+      reads(stage_base(0), I0{}, I0{});
+      // A stage is split around the barrier that makes the next stage
+      // readable: its k step 0 fragments are read before the stage starts,
+      // those of k step 1 while the k step 0 products run; after the barrier
+      // the next stage's k step 0 fragments are read while this stage's
+      // k step 1 products run.
+      for (int st = 0; st < nst; ++st) {
+        reads(stage_base(st), I1{}, I1{});
+        mmas(I0{}, I0{}, IM{});
+        interleave(IM{});
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 1 < nst) {
+          next_stage(st);
+          reads(stage_base(st + 1), I0{}, I0{});
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        mmas(I1{}, I0{}, IM{});
       }
-      __builtin_amdgcn_sched_barrier(0);
-      tail_products();
+    } else {
+      // One k step per stage, fragments double-buffered. Step st opens with
+      // the barrier after which stage st + 1 is readable and every wave has
+      // read stage st; then the 16 NSPLIT MFMAs of stage st run interleaved
+      // with the fragment reads of stage st + 1 and the direct loads of stage
+      // st + NBUF into the buffer stage st leaves free (issued in one burst,
+      // those loads would hold up the MFMAs queued behind them). Every step
+      // issues its loads (beyond the last stage they repeat it, into a buffer
+      // no stage reads), so exactly NBUF - 2 newer stages are outstanding at
+      // each barrier. Steps go in pairs, one fragment slot each; an odd count
+      // starts with a step on zero fragments (its products add exact zeros),
+      // so that no MFMA sits in a branch.
+      auto load_stage = [&](int q) __attribute__((always_inline)) {
+        issue(q % NBUF, kpos(q < nst ? q : nst - 1));
+      };
+      auto open_step = [&](int st) __attribute__((always_inline)) {
+        wait_barrier<(NBUF - 2) * LPS>();
+        if (st + 1 < nst) guard_mask(st + 1);
+      };
+      auto step = [&](int st, auto FI) __attribute__((always_inline)) {
+        constexpr int f = decltype(FI)::value, fn = 1 - f, RD = 4 * NT;
+        open_step(st);
+        const u16* nb = stage_base(st + 1);
+        const int q = st + NBUF;
+        const int64_t kq = kpos(q < nst ? q : nst - 1);
+        // chunk g: direct load g, its share of the fragment reads and of the
+        // MFMAs, fenced so that the loads stay spread over the MFMAs
+        static_for<0, LPS>([&](auto G) {
+          constexpr int g = decltype(G)::value;
+          issue_one(q % NBUF, kq, g / S::IPW, g % S::IPW);
+          static_for<RD * g / LPS, RD * (g + 1) / LPS>([&](auto R) {
+            constexpr int r = decltype(R)::value;
+            fr[fn][r / 4][r % 4] = frag(nb, r / 4, 0, r % 4);
+          });
+          mmas(FI, std::integral_constant<int, MF * g / LPS>{}, std::integral_constant<int, MF * (g + 1) / LPS>{});
+          __builtin_amdgcn_sched_barrier(0);
+        });
+      };
+#pragma unroll
+      for (int p = 0; p < NBUF - 1; ++p) load_stage(p);
+      if (nst & 1) {
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) fr[0][tt][b] = u32x4{0u, 0u, 0u, 0u};
+      } else {
+        open_step(-1);
+        reads(stage_base(0), I0{}, I0{});
+        load_stage(NBUF - 1);
+      }
+      for (int st = -(nst & 1); st < nst; st += 2) {
+        step(st, I0{});
+        step(st + 1, I1{});
+      }
     }
     wait_barrier<0>();
   }
@@ -666,7 +755,7 @@ static int64_t lp_grid(const GemmBatch& bt, int tiles) {
 
 template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
 static hipError_t go_lp(const LpGemmArgs& a, hipStream_t s, int64_t total) {
-  typedef LpShape<NSPLIT> S;
+  typedef LpShape<NSPLIT, lp_kt(NSPLIT, KLO)> S;
   const size_t lds = (size_t)S::NBUF * S::NT * S::TILE * sizeof(unsigned short);
   auto k = k_gemm_lp<F16, NSPLIT, AM, BM, TILES, ORDER, KLO, KHI, EPI>;
   static bool attr_set = false;  // per instantiation
@@ -693,7 +782,7 @@ static hipError_t dispatch_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_
   // panel-blocked planes (zero outside their triangles, no masks)
   if (c.amask == 0 && c.bmask == 0 && c.tiles == kLowerTiles && c.order == kDiagDesc && c.klo == kLoN0Pb &&
       c.khi == kHiM1) {
-    // K = 32 per stage: two stages for 3 products, three for 2 products
+    // K = 16 per stage for 2 or 3 products, 32 for one
     if (c.epi == kLpEpResid && c.nsplit == 3)
       return go_lp<F16, 3, 0, 0, kLowerTiles, kDiagDesc, kLoN0Pb, kHiM1, kLpEpResid>(a, s, total);
     if (c.epi == kLpEpResid && c.nsplit == 2)
