@@ -34,6 +34,10 @@ namespace trinv {
 namespace {
 constexpr int LT = 256;  // workgroup tile (rows and columns)
 constexpr int kTrLd = LT + 8;  // row length of a transposed tile staged in LDS (16-byte rows, fewer bank conflicts)
+// Residual epilogue staging in LDS (after the main loop): diagonals of L and
+// X at kEpDiagOff (4 KB), per-wave X / L blocks at kEpStageOff (128 KB); the
+// first bytes hold the final reduction.
+constexpr int kEpDiagOff = 1024, kEpStageOff = 8192, kEpLdsBytes = kEpStageOff + 4 * 4 * 8192;
 
 // K per LDS stage: 16 (one MFMA k step) for the 2- and 3-product forms on
 // panel-blocked planes, whose stages are large (three or four staged tiles),
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   // NBUF stages x NT tiles x TILE elements (all of the CU's LDS); after the
   // main loop its first bytes hold the per-wave partial sums of the residual
   extern __shared__ __attribute__((aligned(16))) u16 lds[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
 
   const GemmBatch bt = a.bt;
@@ -177,6 +181,11 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   if (B >= nblk) return;
   int64_t z, bi, bj;
   decode_lp<TILES, ORDER>(B, nz, bm, bn, z, bi, bj);
+  // the decode runs on vector instructions; its results are wave-uniform,
+  // and scalar copies keep the tile's address and stage bookkeeping scalar
+  z = __builtin_amdgcn_readfirstlane((int)z);
+  bi = __builtin_amdgcn_readfirstlane((int)bi);
+  bj = __builtin_amdgcn_readfirstlane((int)bj);
   const int64_t it = bi * GB + pos % GB, jt = bj * GB + pos / GB;
   // slot of this tile in the per-tile partial sums (lower tiles packed)
   const int64_t t = (TILES == kLowerTiles) ? z * tm * (tm + 1) / 2 + it * (it + 1) / 2 + jt : (z * tm + it) * tn + jt;
@@ -359,7 +368,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   constexpr int NBUF = S::NBUF;
   constexpr int LPS = S::LPS;
   if (klo < khi) {
-    const int nst = (int)((khi - klo + S::KT - 1) / S::KT);
+    const int nst = __builtin_amdgcn_readfirstlane((int)((khi - klo + S::KT - 1) / S::KT));
     // Stage order. The tiles of a block (panel-blocked products) share row
     // and column panels but start K at their own diagonal offsets; so that
     // the tiles sharing a panel read the same k at the same time (and the
@@ -493,6 +502,38 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
   const double* __restrict__ dLr = a.dL;
   const double* __restrict__ dXr = a.dX;
   const float* __restrict__ R32r = a.R32;
+  // Interior residual tile with 16-byte aligned X and L: each wave stages
+  // the FP64 X and L elements of its 32 x 32 blocks in LDS by direct loads,
+  // one block ahead (two slots per wave, free after the main loop), so that
+  // a block's loads are in flight while the previous block is computed and
+  // stored; the diagonals of L (tile rows) and X (tile columns) are staged
+  // once. Same arithmetic and order as the block-by-block form below.
+  const bool staged = EPI == kLpEpResid && full &&
+                      ((((uintptr_t)a.X) | ((uintptr_t)a.L) | (uintptr_t)(a.ldx * 8) | (uintptr_t)(a.ldl * 8)) & 15) == 0;
+  double* const dls = (double*)((char*)lds + kEpDiagOff);  // dL[m0 + r], r < 256
+  double* const dxs = dls + LT;                            // dX[n0 + c], c < 256
+  // direct loads of block b of this wave into slot b % 2: [slot][X, L][32 rows][32 doubles]
+  auto fetch = [&](auto BI) __attribute__((always_inline)) {
+    constexpr int b = decltype(BI)::value, i = b / 4, j = b % 4, sl = b & 1;
+    typedef __attribute__((address_space(3))) char lds_char;
+    lds_char* const dst = (lds_char*)lds + kEpStageOff + (wave * 4 + 2 * sl) * 8192;
+    const int64_t r0b = m0 + wm * 128 + i * 32 + (lane >> 4), c0b = n0 + wn * 128 + j * 32 + (lane & 15) * 2;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      __builtin_amdgcn_global_load_lds((const void*)(Xr + (r0b + 4 * t) * a.ldx + c0b),
+                                       (__attribute__((address_space(3))) void*)(dst + t * 1024), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(Lr + (r0b + 4 * t) * a.ldl + c0b),
+                                       (__attribute__((address_space(3))) void*)(dst + 8192 + t * 1024), 16, 0, 0);
+    }
+  };
+  if constexpr (EPI == kLpEpResid) {
+    if (staged) {
+      dls[tid] = dLr[m0 + tid];
+      dxs[tid] = dXr[n0 + tid];
+      __syncthreads();
+      fetch(std::integral_constant<int, 0>{});
+    }
+  }
   static_for<0, 16>([&](auto IJ) {
       constexpr int i = decltype(IJ)::value / 4, j = decltype(IJ)::value % 4;
       const f32x16 blk = acc[i][j];
@@ -526,6 +567,61 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
           v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
           v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
           *(uint2*)(lds + (col - n0) * kTrLd + (row0 - m0)) = v;  // transposed tile, stored below
+        }
+      }
+      if constexpr (EPI == kLpEpResid) {
+        if (staged) {
+          constexpr int b = decltype(IJ)::value, sl = b & 1;
+          __builtin_amdgcn_sched_barrier(0);
+          if constexpr (b + 1 < 16) fetch(std::integral_constant<int, b + 1>{});
+          __builtin_amdgcn_sched_barrier(0);
+          // This block's 16 loads done. Vector memory operations complete in
+          // issue order; issued after them: the previous block's 16 R32
+          // stores (and 4 Rt stores, then waited for too) and the next
+          // block's 16 loads.
+          constexpr int VM = (b + 1 < 16 ? 16 : 0) + (b >= 1 ? 16 : 0);
+          asm volatile("" ::: "memory");
+          __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4) | (15 << 8));
+          asm volatile("" ::: "memory");
+          const double* xsl = (const double*)((char*)lds + kEpStageOff + (wave * 4 + 2 * sl) * 8192);
+          const double* lsl = xsl + 1024;
+          const int cl = wn * 128 + j * 32 + (lane & 31), rl = wm * 128 + i * 32 + 4 * (lane >> 5);
+          const int64_t col = n0 + cl, rbase = m0 + rl;
+          // all LDS reads of the block first, then the arithmetic
+          const double xjj = dxs[cl];
+          double xv[16], ov[16], dv[16], rv[16];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const int lrow = 4 * (lane >> 5) + 8 * (k >> 2) + (k & 3);
+            xv[k] = xsl[lrow * 32 + (lane & 31)];
+            ov[k] = lsl[lrow * 32 + (lane & 31)];
+            dv[k] = dls[rl + 8 * (k >> 2) + (k & 3)];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const int64_t row = rbase + 8 * (k >> 2) + (k & 3);
+            const bool ok = col <= row;
+            const double v =
+                (row == col) ? fma(-dv[k], xv[k], 1.0) : -(alpha * (double)blk[k]) - dv[k] * xv[k] - ov[k] * xjj;
+            rv[k] = ok ? v : 0.0;
+            a.R32[row * a.ldr + col] = (float)rv[k];
+            sq += rv[k] * rv[k];
+            sqx += ok ? xv[k] * xv[k] : 0.0;
+          }
+          if (a.Rt) {  // uniform: the FP16 path writes R in low precision in a separate pass
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              u16 o[4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) o[e] = to_lp<F16>((float)(rv[4 * q + e] * a.lp_scale));
+              uint2 v;
+              v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
+              v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
+              *(uint2*)((u16*)a.Rt + pb_index(col, rbase + 8 * q, a.ldrt)) = v;
+            }
+          }
+          return;
         }
       }
       if constexpr (EPI == kLpEpResid || EPI == kLpEpCorr) {
@@ -756,7 +852,8 @@ static int64_t lp_grid(const GemmBatch& bt, int tiles) {
 template <int F16, int NSPLIT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EPI>
 static hipError_t go_lp(const LpGemmArgs& a, hipStream_t s, int64_t total) {
   typedef LpShape<NSPLIT, lp_kt(NSPLIT, KLO)> S;
-  const size_t lds = (size_t)S::NBUF * S::NT * S::TILE * sizeof(unsigned short);
+  size_t lds = (size_t)S::NBUF * S::NT * S::TILE * sizeof(unsigned short);
+  if (EPI == kLpEpResid && lds < (size_t)kEpLdsBytes) lds = kEpLdsBytes;
   auto k = k_gemm_lp<F16, NSPLIT, AM, BM, TILES, ORDER, KLO, KHI, EPI>;
   static bool attr_set = false;  // per instantiation
   if (!attr_set) {
