@@ -7,10 +7,10 @@
 // v_mfma_f32_32x32x16_{bf16,f16}; each wave owns a 128 x 128 sub-tile
 // (4 x 4 blocks of 32 x 32, 256 FP32 accumulators per lane). Both operands
 // are k-contiguous in memory (B is stored transposed), so a K step is staged
-// by direct global -> LDS 16-byte loads into a ring of five LDS stages (at
-// most 160 KB: K = 32 per stage for one product, K = 16 for the 2- and
-// 3-product forms), issued one stage short of the ring ahead, and every MFMA
-// operand is one 16-byte LDS read. Lane
+// by direct global -> LDS 16-byte loads into a ring of LDS stages (at most
+// 160 KB: five of K = 32 for the single products, five or six of K = 16 for
+// the 2- and 3-product residuals), issued one stage short of the ring ahead, and
+// every MFMA operand is one 16-byte LDS read. Lane
 // layouts (measured on gfx950): lane l supplies A(l%32, 8(l/32)+e) and
 // B(8(l/32)+e, l%32), e = 0..7, and receives D(8(r/4) + 4(l/32) + r%4, l%32)
 // in register r.
@@ -39,9 +39,9 @@ constexpr int kTrLd = LT + 8;  // row length of a transposed tile staged in LDS 
 // first bytes hold the final reduction.
 constexpr int kEpDiagOff = 1024, kEpStageOff = 8192, kEpLdsBytes = kEpStageOff + 4 * 4 * 8192;
 
-// K per LDS stage: 16 (one MFMA k step) for the 2- and 3-product forms on
-// panel-blocked planes, whose stages are large (three or four staged tiles),
-// so that five stages fit and loads run four stages ahead; 32 otherwise.
+// K per LDS stage: 16 (one MFMA k step) for the 2- and 3-product residuals
+// on panel-blocked planes, whose loads are spread over the MFMAs of the
+// stage before and run four or five stages ahead; 32 for the other products.
 constexpr int lp_kt(int nsplit, int klo) { return (klo == kLoN0Pb && nsplit >= 2) ? 16 : 32; }
 
 template <int NSPLIT, int KT_>
@@ -54,11 +54,13 @@ struct LpShape {
   static constexpr int IPW = KT / 8;                // direct-load instructions per wave per tile
   static constexpr int LPS = NT * IPW;              // direct loads per thread and stage
   static constexpr int RSW = 128 / KT;              // rows per swizzle step
-  // LDS stages (at most 160 KB, at most 5, and at most 63 loads of newer
-  // stages outstanding per thread): loads run NBUF - 1 stages ahead
+  // LDS stages (at most 160 KB, at most 5 of K = 32 or 8 of K = 16, and at
+  // most 63 loads of newer stages outstanding per thread): loads run
+  // NBUF - 1 stages ahead
   static constexpr int NB_LDS = 163840 / (NT * LT * KT * 2);
   static constexpr int NB_VM = 1 + 63 / LPS;
-  static constexpr int NBUF = NB_LDS < NB_VM ? (NB_LDS < 5 ? NB_LDS : 5) : (NB_VM < 5 ? NB_VM : 5);
+  static constexpr int NB_MAX = KT == 16 ? 8 : 5;
+  static constexpr int NBUF = NB_LDS < NB_VM ? (NB_LDS < NB_MAX ? NB_LDS : NB_MAX) : (NB_VM < NB_MAX ? NB_VM : NB_MAX);
   static_assert(NBUF >= 2, "two stages at least");
   static_assert(KT == 16 || KT == 32, "one or two MFMA k steps per stage");
   // Chunk position p of row r holds the row's k-chunk p ^ swz(r): 16
