@@ -322,51 +322,35 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  // Fragments: fr[slot][tile][block], one slot per MFMA k step in flight
-  // (slot = k step within the stage when a stage holds two k steps, stage
-  // parity when it holds one). Products of a k step (A tile x B tile):
-  // A_hi B_hi (1); A_lo B_hi, A_hi B_hi (2); A_hi B_lo, A_lo B_hi, A_hi B_hi (3).
-  constexpr int KS = S::KT / 16, NT = S::NT, MF = 16 * NSPLIT;
-  u32x4 fr[2][NT][4];
+  // Fragments: fr[KS slot + ks][tile][block], two slots (stage parity) of KS
+  // k steps each. Products of a k step (A tile x B tile): A_hi B_hi (1);
+  // A_lo B_hi, A_hi B_hi (2); A_hi B_lo, A_lo B_hi, A_hi B_hi (3).
+  constexpr int KS = S::KT / 16, NT = S::NT, MF = 16 * NSPLIT, RD = 4 * NT;
+  static_assert(KS * NT <= 4, "two slots of fragments fit in 128 registers");
+  u32x4 fr[2 * KS][NT][4];
   auto prod_a = [](int p) constexpr { return NSPLIT == 1 ? 0 : (NSPLIT == 2 ? (p == 0 ? 2 : 0) : (p == 1 ? 2 : 0)); };
   auto prod_b = [](int p) constexpr { return NSPLIT == 3 ? (p == 0 ? 3 : 1) : 1; };
-  auto read_tile = [&](const u16* base, auto FI, auto KSI, auto TTI) __attribute__((always_inline)) {
-    constexpr int f = decltype(FI)::value, ks = decltype(KSI)::value, tt = decltype(TTI)::value;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) fr[f][tt][b] = frag(base, tt, 16 * ks, b);
+  // fragment reads [LO, HI) of a stage's KS RD (k step, then tile, block) into slot f
+  auto freads = [&](const u16* base, auto FI, auto LOI, auto HII) __attribute__((always_inline)) {
+    constexpr int f = decltype(FI)::value;
+    static_for<decltype(LOI)::value, decltype(HII)::value>([&](auto RI) {
+      constexpr int r = decltype(RI)::value, ks = r / RD, rr = r % RD;
+      fr[f * KS + ks][rr / 4][rr % 4] = frag(base, rr / 4, 16 * ks, rr % 4);
+    });
   };
-  auto reads = [&](const u16* base, auto FI, auto KSI) __attribute__((always_inline)) {
-    static_for<0, NT>([&](auto T) { read_tile(base, FI, KSI, T); });
-  };
-  // MFMAs [LO, HI) of a k step's MF = 16 NSPLIT (product-major, then i, j)
+  // MFMAs [LO, HI) of a stage's KS MF (k step, then product, i, j) from slot f
   auto mmas = [&](auto FI, auto LOI, auto HII) __attribute__((always_inline)) {
     constexpr int f = decltype(FI)::value;
     static_for<decltype(LOI)::value, decltype(HII)::value>([&](auto MI) {
-      constexpr int m = decltype(MI)::value, p = m / 16, i = (m / 4) % 4, j = m % 4;
-      acc[i][j] = mma<F16>(fr[f][prod_a(p)][i], fr[f][prod_b(p)][j], acc[i][j]);
+      constexpr int m = decltype(MI)::value, ks = m / MF, mm = m % MF, p = mm / 16, i = (mm / 4) % 4, j = mm % 4;
+      acc[i][j] = mma<F16>(fr[f * KS + ks][prod_a(p)][i], fr[f * KS + ks][prod_b(p)][j], acc[i][j]);
     });
-  };
-  // interleave the last NMF MFMAs issued with the 4 NT fragment reads issued
-  // beside them
-  auto interleave = [](auto NMFI) __attribute__((always_inline)) {
-    constexpr int RD = 4 * NT, NMF = decltype(NMFI)::value, Q = NMF / RD, REM = NMF - Q * RD;
-#pragma unroll
-    for (int g = 0; g < RD; ++g) {
-      __builtin_amdgcn_sched_group_barrier(0x008, Q, 0);  // MFMA
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
-    }
-    if (REM) __builtin_amdgcn_sched_group_barrier(0x008, REM, 0);
   };
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
-  using IH = std::integral_constant<int, MF / 2>;
-  using IM = std::integral_constant<int, MF>;
 
-  // NBUF-stage pipeline: stage st lives in buffer st % NBUF. The loads of
-  // stages 0 .. NBUF - 1 are issued up front; stage st + NBUF is issued into
-  // the buffer of stage st once every wave has read stage st (the barrier
-  // that makes stage st + 1 readable). Before that barrier each wave waits
-  // until only its loads of the newer stages are outstanding.
+  // NBUF-stage pipeline: stage st lives in buffer st % NBUF; the loads of
+  // stage st + NBUF go into the buffer stage st leaves free.
   constexpr int NBUF = S::NBUF;
   constexpr int LPS = S::LPS;
   if (klo < khi) {
@@ -386,12 +370,6 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
     auto kpos = [&](int st) -> int64_t {
       return (int64_t)S::KT * (st < nst - a_s ? a_s + st : nst - 1 - st);
     };
-    auto ready = [&](int st) __attribute__((always_inline)) {
-      if (st + NBUF - 2 < nst)
-        wait_barrier<(NBUF - 2) * LPS>();
-      else
-        wait_barrier<0>();
-    };
     auto guard_mask = [&](int st) __attribute__((always_inline)) {
       const int64_t k0 = klo + kpos(st);
       bool guard = (k0 + S::KT > K);
@@ -403,92 +381,57 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
       }
     };
     auto stage_base = [&](int st) { return lds + (st % NBUF) * (NT * S::TILE); };
-    // the barrier before stage st + 1: wait, refill the buffer of stage st,
-    // mask stage st + 1 if needed
-    auto next_stage = [&](int st) __attribute__((always_inline)) {
-      ready(st + 1);  // also: every wave has read stage st
-      if (st + NBUF < nst) issue(st % NBUF, kpos(st + NBUF));
-      guard_mask(st + 1);
+    // Step st opens with the barrier after which stage st + 1 is readable and
+    // every wave has read stage st; then the KS MF MFMAs of stage st run
+    // interleaved with the fragment reads of stage st + 1 and the direct
+    // loads of stage st + NBUF into the buffer stage st leaves free (issued in
+    // one burst, those loads would hold up the MFMAs queued behind them).
+    // Every step issues its loads (beyond the last stage they repeat it, into
+    // a buffer no stage reads), so exactly NBUF - 2 newer stages are
+    // outstanding at each barrier. Steps go in pairs, one fragment slot each;
+    // an odd count starts with a step on zero fragments (its products add
+    // exact zeros), so that no MFMA sits in a branch.
+    auto load_stage = [&](int q) __attribute__((always_inline)) {
+      issue(q % NBUF, kpos(q < nst ? q : nst - 1));
     };
-    if constexpr (KS == 2) {
-#pragma unroll
-      for (int p = 0; p < NBUF - 1; ++p)
-        if (p < nst) issue(p, kpos(p));
-      ready(0);
-      if (NBUF - 1 < nst) issue(NBUF - 1, kpos(NBUF - 1));
-      guard_mask(0);
-      reads(stage_base(0), I0{}, I0{});
-      // A stage is split around the barrier that makes the next stage
-      // readable: its k step 0 fragments are read before the stage starts,
-      // those of k step 1 while the k step 0 products run; after the barrier
-      // the next stage's k step 0 fragments are read while this stage's
-      // k step 1 products run.
-      for (int st = 0; st < nst; ++st) {
-        reads(stage_base(st), I1{}, I1{});
-        mmas(I0{}, I0{}, IM{});
-        interleave(IM{});
+    auto open_step = [&](int st) __attribute__((always_inline)) {
+      wait_barrier<(NBUF - 2) * LPS>();
+      if (st + 1 < nst) guard_mask(st + 1);
+    };
+    auto step = [&](int st, auto FI) __attribute__((always_inline)) {
+      using FN = std::integral_constant<int, 1 - decltype(FI)::value>;
+      open_step(st);
+      const u16* nb = stage_base(st + 1);
+      const int q = st + NBUF;
+      const int64_t kq = kpos(q < nst ? q : nst - 1);
+      // chunk g: direct load g, its share of the fragment reads and of the
+      // MFMAs, fenced so that the loads stay spread over the MFMAs
+      static_for<0, LPS>([&](auto G) {
+        constexpr int g = decltype(G)::value;
+        issue_one(q % NBUF, kq, g / S::IPW, g % S::IPW);
+        freads(nb, FN{}, std::integral_constant<int, KS * RD * g / LPS>{},
+               std::integral_constant<int, KS * RD * (g + 1) / LPS>{});
+        mmas(FI, std::integral_constant<int, KS * MF * g / LPS>{}, std::integral_constant<int, KS * MF * (g + 1) / LPS>{});
         __builtin_amdgcn_sched_barrier(0);
-        if (st + 1 < nst) {
-          next_stage(st);
-          reads(stage_base(st + 1), I0{}, I0{});
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        mmas(I1{}, I0{}, IM{});
-      }
-    } else {
-      // One k step per stage, fragments double-buffered. Step st opens with
-      // the barrier after which stage st + 1 is readable and every wave has
-      // read stage st; then the 16 NSPLIT MFMAs of stage st run interleaved
-      // with the fragment reads of stage st + 1 and the direct loads of stage
-      // st + NBUF into the buffer stage st leaves free (issued in one burst,
-      // those loads would hold up the MFMAs queued behind them). Every step
-      // issues its loads (beyond the last stage they repeat it, into a buffer
-      // no stage reads), so exactly NBUF - 2 newer stages are outstanding at
-      // each barrier. Steps go in pairs, one fragment slot each; an odd count
-      // starts with a step on zero fragments (its products add exact zeros),
-      // so that no MFMA sits in a branch.
-      auto load_stage = [&](int q) __attribute__((always_inline)) {
-        issue(q % NBUF, kpos(q < nst ? q : nst - 1));
-      };
-      auto open_step = [&](int st) __attribute__((always_inline)) {
-        wait_barrier<(NBUF - 2) * LPS>();
-        if (st + 1 < nst) guard_mask(st + 1);
-      };
-      auto step = [&](int st, auto FI) __attribute__((always_inline)) {
-        constexpr int f = decltype(FI)::value, fn = 1 - f, RD = 4 * NT;
-        open_step(st);
-        const u16* nb = stage_base(st + 1);
-        const int q = st + NBUF;
-        const int64_t kq = kpos(q < nst ? q : nst - 1);
-        // chunk g: direct load g, its share of the fragment reads and of the
-        // MFMAs, fenced so that the loads stay spread over the MFMAs
-        static_for<0, LPS>([&](auto G) {
-          constexpr int g = decltype(G)::value;
-          issue_one(q % NBUF, kq, g / S::IPW, g % S::IPW);
-          static_for<RD * g / LPS, RD * (g + 1) / LPS>([&](auto R) {
-            constexpr int r = decltype(R)::value;
-            fr[fn][r / 4][r % 4] = frag(nb, r / 4, 0, r % 4);
-          });
-          mmas(FI, std::integral_constant<int, MF * g / LPS>{}, std::integral_constant<int, MF * (g + 1) / LPS>{});
-          __builtin_amdgcn_sched_barrier(0);
-        });
-      };
+      });
+    };
 #pragma unroll
-      for (int p = 0; p < NBUF - 1; ++p) load_stage(p);
-      if (nst & 1) {
+    for (int p = 0; p < NBUF - 1; ++p) load_stage(p);
+    if (nst & 1) {
+#pragma unroll
+      for (int f = 0; f < KS; ++f)
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) fr[0][tt][b] = u32x4{0u, 0u, 0u, 0u};
-      } else {
-        open_step(-1);
-        reads(stage_base(0), I0{}, I0{});
-        load_stage(NBUF - 1);
-      }
-      for (int st = -(nst & 1); st < nst; st += 2) {
-        step(st, I0{});
-        step(st + 1, I1{});
-      }
+          for (int b = 0; b < 4; ++b) fr[f][tt][b] = u32x4{0u, 0u, 0u, 0u};
+    } else {
+      open_step(-1);
+      freads(stage_base(0), I0{}, I0{}, std::integral_constant<int, KS * RD>{});
+      load_stage(NBUF - 1);
+    }
+    for (int st = -(nst & 1); st < nst; st += 2) {
+      step(st, I0{});
+      step(st + 1, I1{});
     }
     wait_barrier<0>();
   }
