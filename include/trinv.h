@@ -207,13 +207,20 @@ size_t trinv_batched_workspace_bytes(int mode, int64_t batch, const int32_t *n_h
  *     of the first zero diagonal of matrix i (X_i then holds non-finite
  *     values), or -1 if n_dev[i] is outside [1, 1024], or -2 if X_i holds a
  *     NaN or an infinity (a non-finite input entry, or overflow).
- *   opts: leaf 0 (tuned or default), 32 or 64 (else TRINV_ERR_ARG); unit_diag honoured; upper is
- *     TRINV_ERR_UNSUPPORTED; blocking: wait and return TRINV_ERR_SINGULAR if
- *     any matrix is singular, else TRINV_ERR_NONFINITE if any status is -2.
- *   ws: at least trinv_batched_workspace_bytes bytes, caller-owned.
+ *   opts: leaf 0 (tuned or default), 32 or 64 (else TRINV_ERR_ARG); unit_diag honoured;
+ *     upper: the matrices are UPPER triangular (only their upper triangles
+ *     are read) and X_i = U_i^-1 is upper (zeros below the diagonal),
+ *     through the transpose, (U^T)^-1 = (U^-1)^T (Section 2); blocking: wait
+ *     and return TRINV_ERR_SINGULAR if any matrix is singular, else
+ *     TRINV_ERR_NONFINITE if any status is -2.
+ *   ws: at least trinv_batched_workspace_bytes bytes (which depends on
+ *     opts->upper), caller-owned.
  * Two launches on `stream`: a one-workgroup plan kernel (sorts the matrices
  * by order, largest first, and resets the queue counter in ws) and one
  * persistent kernel whose workgroups take whole matrices from that queue.
+ * With upper, three more: the dense offsets, the transposes U_i^T into ws
+ * (packed back to back), and X_i as the transposes of their lower inverses
+ * (also held in ws).
  * No memset and no host synchronisation (unless blocking), so the call can be
  * captured in a graph and replayed.
  */
@@ -231,7 +238,8 @@ int trinv_tril_inverse_batched(int mode, int64_t batch, const int32_t *n_host, c
  * the library runs on until the process ends) instead of a workspace. No
  * device memory is allocated or freed, by the library or anything it calls.
  * Arguments, status values and errors as trinv_tril_inverse_batched, without
- * ws / ws_bytes; batch > 65536 gives TRINV_ERR_ARG. Every call on one device
+ * ws / ws_bytes; batch > 65536 gives TRINV_ERR_ARG, and opts->upper
+ * TRINV_ERR_UNSUPPORTED (its transposed staging needs a workspace). Every call on one device
  * shares that device's scratch (the plan kernel rewrites the plan and resets
  * the counter at the start of each call), so calls that overlap on one
  * device -- on different streams, or from different threads -- race and
@@ -261,11 +269,19 @@ typedef struct {
  * batch's order signature (mode, count, sum of n_i, sum of n_i^2, largest n_i)
  * for the rest of the process: later trinv_tril_inverse_batched calls with
  * the same signature use it (the default is leaf 64 for FP32, 32 for FP64,
- * and the occupancy limit). Arguments and errors as
+ * and the occupancy limit). opts->upper gives TRINV_ERR_UNSUPPORTED: the
+ * configuration tuned on the lower form serves upper calls with the same
+ * orders. Arguments and errors as
  * trinv_tril_inverse_batched. On return X_packed and status_dev hold the
  * result of the chosen configuration; `out` (nullable) receives it. Uniform
  * batches that take the level path have nothing to tune (out->ms = -1).
  * Synchronises `stream` (not for graph capture: tune first, then capture).
+ * If the environment variable TRINV_TUNE_CACHE names a file, every result is
+ * appended to it as a line "device mode count sum sum_sq largest leaf
+ * wgs_per_cu ms" (device: architecture name / CU count), and the first
+ * lookup of a process loads that file's lines for the current device, so a
+ * later process reuses them without tuning (a missing or unreadable file is
+ * ignored).
  */
 int trinv_batched_autotune(int mode, int64_t batch, const int32_t *n_host, const int32_t *n_dev,
                            const int64_t *off_host, const int64_t *off_dev, const void *L_packed,
@@ -277,6 +293,13 @@ int trinv_batched_autotune(int mode, int64_t batch, const int32_t *n_host, const
  * one an earlier process found. cfg->leaf 32 or 64, cfg->wgs_per_cu >= 0 (0
  * or above the occupancy limit: that limit); else TRINV_ERR_ARG. */
 int trinv_batched_set_config(int mode, int64_t batch, const int32_t *n_host, const trinv_batched_config *cfg);
+
+/* The configuration the next trinv_tril_inverse_batched call with this
+ * order signature would use (set, tuned in this process, or loaded from the
+ * TRINV_TUNE_CACHE file; otherwise the default leaf and wgs_per_cu = 0);
+ * cfg->ms = -1. TRINV_ERR_ARG for batch <= 0, a null pointer or an order
+ * outside 1..1024; TRINV_ERR_UNSUPPORTED for modes other than F64 / F32. */
+int trinv_batched_get_config(int mode, int64_t batch, const int32_t *n_host, trinv_batched_config *cfg);
 
 /*
  * Adjoint of X = L^-1 for a strided batch of lower-triangular matrices:

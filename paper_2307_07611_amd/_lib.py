@@ -23,7 +23,7 @@ RESID = {"auto": RESID_AUTO, "split": RESID_SPLIT, "fp64": RESID_FP64}
 EXPORTS = [
     "trinv_default_opts", "trinv_status_string", "trinv_workspace_bytes", "trinv_tril_inverse",
     "trinv_batched_workspace_bytes", "trinv_tril_inverse_batched", "trinv_batched_autotune",
-    "trinv_batched_set_config", "trinv_tril_inverse_batched_noalloc",
+    "trinv_batched_set_config", "trinv_batched_get_config", "trinv_tril_inverse_batched_noalloc",
     "trinv_backward_workspace_bytes",
     "trinv_tril_inverse_backward", "trinv_factored_workspace_bytes", "trinv_factored_inverse",
     "trinv_residual_workspace_bytes", "trinv_residual", "trinv_refine_residual_workspace_bytes",
@@ -91,6 +91,8 @@ def load():
     lib.trinv_batched_autotune.restype = ctypes.c_int
     lib.trinv_batched_set_config.argtypes = [ctypes.c_int, _i64, _vp, ctypes.POINTER(BatchedConfig)]
     lib.trinv_batched_set_config.restype = ctypes.c_int
+    lib.trinv_batched_get_config.argtypes = [ctypes.c_int, _i64, _vp, ctypes.POINTER(BatchedConfig)]
+    lib.trinv_batched_get_config.restype = ctypes.c_int
     lib.trinv_backward_workspace_bytes.argtypes = [ctypes.c_int, _i64, _i64]
     lib.trinv_backward_workspace_bytes.restype = _sz
     lib.trinv_tril_inverse_backward.argtypes = [ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _sz, _vp]

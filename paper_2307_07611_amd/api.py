@@ -171,11 +171,12 @@ def factored_inverse(L: torch.Tensor, U: torch.Tensor, *, l_unit=False, u_unit=F
 
 
 def tril_inverse_batched(L_packed: torch.Tensor, sizes, offsets=None, mode=None, *, blocking=True, leaf=0,
-                         out=None, workspace=None, n_dev=None, off_dev=None, status=None):
+                         upper=False, out=None, workspace=None, n_dev=None, off_dev=None, status=None):
     """Inverse of every matrix of a packed batch (dense n_i x n_i blocks at
     element offsets ``offsets``); returns (X_packed, status per matrix).
     Uneven orders run in one persistent launch (after a one-block plan
-    kernel); uniform ones as batched level products."""
+    kernel); uniform ones as batched level products. ``upper``: the matrices
+    are upper triangular (inverted through their transposes)."""
     _check_dev(L_packed)
     import numpy as np
 
@@ -196,7 +197,7 @@ def tril_inverse_batched(L_packed: torch.Tensor, sizes, offsets=None, mode=None,
     if status is None:
         status = torch.empty(batch, dtype=torch.int32, device=dev)
     lib = _lib.load()
-    o = _opts(leaf=leaf, blocking=blocking)
+    o = _opts(leaf=leaf, blocking=blocking, upper=upper)
     nbytes = lib.trinv_batched_workspace_bytes(m, batch, sizes_np.ctypes.data, ctypes.byref(o))
     ws = workspace if workspace is not None else _workspace(nbytes, dev)
     st = lib.trinv_tril_inverse_batched(m, batch, sizes_np.ctypes.data, n_dev.data_ptr(), off_np.ctypes.data,
@@ -256,6 +257,21 @@ def batched_set_config(sizes, mode, leaf, wgs_per_cu=0):
                                               ctypes.byref(cfg))
     if st != _lib.OK:
         raise _lib.TrinvError(st, "trinv_batched_set_config")
+
+
+def batched_get_config(sizes, mode) -> dict:
+    """The persistent batched launch's configuration for batches with these
+    orders: set, tuned in this process or loaded from the TRINV_TUNE_CACHE
+    file, else the defaults (trinv_batched_get_config)."""
+    import numpy as np
+
+    sizes_np = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
+    cfg = _lib.BatchedConfig()
+    st = _lib.load().trinv_batched_get_config(_lib.MODES[mode], len(sizes_np), sizes_np.ctypes.data,
+                                              ctypes.byref(cfg))
+    if st != _lib.OK:
+        raise _lib.TrinvError(st, "trinv_batched_get_config")
+    return {"leaf": cfg.leaf, "wgs_per_cu": cfg.wgs_per_cu}
 
 
 def skul(A: torch.Tensor, *, want_ainv=True, leaf=0, blocking=True):

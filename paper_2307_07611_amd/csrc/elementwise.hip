@@ -340,6 +340,81 @@ hipError_t launch_transpose_inplace(T* A, int64_t lda, int64_t n, hipStream_t s)
 template hipError_t launch_transpose_inplace<double>(double*, int64_t, int64_t, hipStream_t);
 template hipError_t launch_transpose_inplace<float>(float*, int64_t, int64_t, hipStream_t);
 
+// Dense offsets of a packed batch, off[i] = sum_{j < i} n_j^2 (orders
+// outside 1..1024 count as 0): one workgroup, 256-element chunks, each an
+// inclusive scan in LDS plus the running total.
+__global__ __launch_bounds__(256) void k_dense_offsets(const int32_t* __restrict__ n, int64_t batch,
+                                                       int64_t* __restrict__ off) {
+  __shared__ int64_t part[256];
+  const int t = threadIdx.x;
+  int64_t carry = 0;
+  for (int64_t base = 0; base < batch; base += 256) {
+    const int64_t i = base + t;
+    const int32_t ni = i < batch ? n[i] : 0;
+    const int64_t v = (ni >= 1 && ni <= 1024) ? (int64_t)ni * ni : 0;
+    part[t] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+      const int64_t add = t >= d ? part[t - d] : 0;
+      __syncthreads();
+      part[t] += add;
+      __syncthreads();
+    }
+    if (i < batch) off[i] = carry + part[t] - v;
+    carry += part[255];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_dense_offsets(const int32_t* n_dev, int64_t batch, int64_t* off, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dense_offsets, dim3(1), dim3(256), 0, s, n_dev, batch, off);
+  return hipGetLastError();
+}
+
+// B_i = A_i^T for every matrix of a packed batch (order n_dev[i], A_i at
+// offset offa[i], B_i at offb[i], leading dimension n_i): block (i, c) moves
+// the 32 x 32 tiles c, c + gridDim.y, ... of matrix i through LDS. Matrices
+// of an order outside 1..1024, or whose B range would end beyond capb
+// elements, are skipped.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_packed(const int32_t* __restrict__ n_dev,
+                                                          const int64_t* __restrict__ offa, const T* __restrict__ A,
+                                                          const int64_t* __restrict__ offb, T* __restrict__ B,
+                                                          int64_t capb) {
+  __shared__ T tile[32][33];
+  const int64_t m = blockIdx.x;
+  const int n = n_dev[m];
+  if (n < 1 || n > 1024 || offb[m] + (int64_t)n * n > capb) return;
+  const T* a = A + offa[m];
+  T* b = B + offb[m];
+  const int nt = (n + 31) / 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int q = blockIdx.y; q < nt * nt; q += gridDim.y) {
+    const int bi = (q / nt) * 32, bj = (q % nt) * 32;
+    for (int r = ty; r < 32; r += 8)
+      if (bi + r < n && bj + tx < n) tile[r][tx] = a[(int64_t)(bi + r) * n + bj + tx];
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8)
+      if (bj + r < n && bi + tx < n) b[(int64_t)(bj + r) * n + bi + tx] = tile[tx][r];  // B(bj+r, bi+tx) = A(bi+tx, bj+r)
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t launch_transpose_packed(int64_t batch, const int32_t* n_dev, const int64_t* offa, const T* A,
+                                   const int64_t* offb, T* B, int64_t capb, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  if (batch > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_transpose_packed<T>), dim3((unsigned)batch, 8), dim3(256), 0, s, n_dev, offa, A, offb, B,
+                     capb);
+  return hipGetLastError();
+}
+template hipError_t launch_transpose_packed<double>(int64_t, const int32_t*, const int64_t*, const double*,
+                                                    const int64_t*, double*, int64_t, hipStream_t);
+template hipError_t launch_transpose_packed<float>(int64_t, const int32_t*, const int64_t*, const float*,
+                                                   const int64_t*, float*, int64_t, hipStream_t);
+
 // *flag |= 1 if the n x n matrix A holds a NaN or an infinity.
 template <typename T>
 __global__ __launch_bounds__(256) void k_nonfinite(const T* __restrict__ A, int64_t n, int64_t lda, int64_t rpb,

@@ -161,6 +161,13 @@ hipError_t launch_transpose(const T* A, int64_t lda, T* B, int64_t ldb, int64_t 
 // A = A^T in place for an n x n matrix.
 template <typename T>
 hipError_t launch_transpose_inplace(T* A, int64_t lda, int64_t n, hipStream_t s);
+// off[i] = sum_{j < i} n_j^2 over the batch's orders (outside 1..1024: 0)
+hipError_t launch_dense_offsets(const int32_t* n_dev, int64_t batch, int64_t* off, hipStream_t s);
+// B_i = A_i^T for every matrix of a packed batch (skips orders outside
+// 1..1024 and B ranges ending beyond capb elements)
+template <typename T>
+hipError_t launch_transpose_packed(int64_t batch, const int32_t* n_dev, const int64_t* offa, const T* A,
+                                   const int64_t* offb, T* B, int64_t capb, hipStream_t s);
 // *flag |= 1 if the n x n matrix A holds a NaN or an infinity (flag: a
 // device word the caller clears).
 template <typename T>

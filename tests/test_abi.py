@@ -180,7 +180,16 @@ def test_batched_argument_errors_before_any_launch(lib):
     up = _lib.Opts()
     lib.trinv_default_opts(ctypes.byref(up))
     up.upper = 1
-    assert call(_lib.F32, 3, n, off, 1 << 30, 1 << 31, 1 << 32, up) == _lib.ERR_UNSUPPORTED
+    # upper input: staged through transposes in the workspace, which grows by
+    # two densely packed copies of the batch and the dense offsets
+    w_lo = lib.trinv_batched_workspace_bytes(_lib.F32, 3, n.ctypes.data, ctypes.byref(o))
+    w_up = lib.trinv_batched_workspace_bytes(_lib.F32, 3, n.ctypes.data, ctypes.byref(up))
+    assert w_up >= w_lo + 2 * 4 * int((n.astype(np.int64) ** 2).sum()) + 8 * 3
+    assert lib.trinv_tril_inverse_batched(_lib.F32, 3, n.ctypes.data, 4096, off.ctypes.data, 8192, 1 << 30,
+                                          1 << 31, 1 << 32, ctypes.byref(up), 1 << 20, w_lo, None) == \
+        _lib.ERR_WORKSPACE
+    assert lib.trinv_tril_inverse_batched_noalloc(_lib.F32, 3, n.ctypes.data, 4096, off.ctypes.data, 8192, 1 << 30,
+                                                  1 << 31, 1 << 32, ctypes.byref(up), None) == _lib.ERR_UNSUPPORTED
     lf = _lib.Opts()
     lib.trinv_default_opts(ctypes.byref(lf))
     for leaf in (16, 128):  # the persistent launch takes leaf 0, 32 or 64
@@ -285,3 +294,30 @@ def test_batched_tuner_argument_errors(lib):
     assert out.ms == -1.0
     assert lib.trinv_batched_autotune(_lib.F32, 3, None, None, None, None, None, None, None, None, None, 0, None,
                                       ctypes.byref(out)) == _lib.ERR_ARG
+
+
+def test_batched_get_config_host_side(lib):
+    """trinv_batched_get_config: argument errors, and the defaults for a
+    signature nothing has set (no device needed)."""
+    import numpy as np
+
+    from paper_2307_07611_amd import _lib
+
+    n = np.array([5, 64, 100], dtype=np.int32)
+    cfg = _lib.BatchedConfig()
+    assert lib.trinv_batched_get_config(_lib.F32, 0, n.ctypes.data, ctypes.byref(cfg)) == _lib.ERR_ARG
+    assert lib.trinv_batched_get_config(_lib.F32, 3, None, ctypes.byref(cfg)) == _lib.ERR_ARG
+    assert lib.trinv_batched_get_config(_lib.F32, 3, n.ctypes.data, None) == _lib.ERR_ARG
+    assert lib.trinv_batched_get_config(_lib.BF16_REFINE, 3, n.ctypes.data, ctypes.byref(cfg)) == \
+        _lib.ERR_UNSUPPORTED
+    bad = np.array([5, 2000, 100], dtype=np.int32)
+    assert lib.trinv_batched_get_config(_lib.F32, 3, bad.ctypes.data, ctypes.byref(cfg)) == _lib.ERR_ARG
+    assert lib.trinv_batched_get_config(_lib.F32, 3, n.ctypes.data, ctypes.byref(cfg)) == _lib.OK
+    assert (cfg.leaf, cfg.wgs_per_cu, cfg.ms) == (64, 0, -1.0)
+    assert lib.trinv_batched_get_config(_lib.F64, 3, n.ctypes.data, ctypes.byref(cfg)) == _lib.OK
+    assert (cfg.leaf, cfg.wgs_per_cu) == (32, 0)
+    # set_config pins a signature for the rest of the process
+    pin = _lib.BatchedConfig(32, 2, -1.0)
+    assert lib.trinv_batched_set_config(_lib.F32, 3, n.ctypes.data, ctypes.byref(pin)) == _lib.OK
+    assert lib.trinv_batched_get_config(_lib.F32, 3, n.ctypes.data, ctypes.byref(cfg)) == _lib.OK
+    assert (cfg.leaf, cfg.wgs_per_cu) == (32, 2)

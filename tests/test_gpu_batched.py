@@ -279,3 +279,111 @@ def test_autotune_f64_uneven(P):
     torch.cuda.synchronize()
     assert int(st2.abs().sum()) == 0
     check(mats, unpack(X2.cpu().numpy(), offs, sizes), TOL["f64"], oracle_every=5)
+
+
+_TUNE_SCRIPT = r"""
+import json, os, sys
+import numpy as np
+import torch
+sys.path.insert(0, os.environ["TRINV_TEST_ROOT"])
+import paper_2307_07611_amd as P
+sizes = np.array([40, 130, 77] * 100, dtype=np.int32)
+sq = sizes.astype(np.int64) ** 2
+offs = np.concatenate([[0], np.cumsum(sq)[:-1]]).astype(np.int64)
+rng = np.random.default_rng(1)
+packed = np.zeros(int(sq.sum()), dtype=np.float32)
+for n, o in zip(sizes, offs):
+    A = np.tril(rng.standard_normal((n, n)) / n, -1) + 2.0 * np.eye(n)
+    packed[o:o + n * n] = A.ravel()
+if sys.argv[1] == "tune":
+    L = torch.from_numpy(packed).cuda()
+    X = torch.empty_like(L)
+    st = torch.empty(len(sizes), dtype=torch.int32, device="cuda")
+    P.batched_autotune(L, sizes, offs, "f32", out=X, status=st)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+else:
+    torch.zeros(1, device="cuda")
+print("CFG " + json.dumps([P.batched_get_config(sizes, "f32"), P.batched_get_config([33] * 500, "f32")]), flush=True)
+"""
+
+
+def test_tune_cache_across_processes(tmp_path):
+    """TRINV_TUNE_CACHE: one process tunes and appends its result; a fresh
+    process loads it without tuning, and a line written for another order
+    signature is honoured; without the variable the defaults apply."""
+    import json
+    import os
+    import subprocess
+    import sys
+
+    banner("batched tuning cache across processes")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    script = tmp_path / "tune_script.py"
+    script.write_text(_TUNE_SCRIPT)
+
+    def run(arg, with_cache=True):
+        env = dict(os.environ, TRINV_TEST_ROOT=root)
+        env.pop("TRINV_TUNE_CACHE", None)
+        if with_cache:
+            env["TRINV_TUNE_CACHE"] = str(cache)
+        r = subprocess.run([sys.executable, str(script), arg], capture_output=True, text=True, env=env, timeout=240)
+        assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+        line = [ln for ln in r.stdout.splitlines() if ln.startswith("CFG ")][-1]
+        return json.loads(line[4:])
+
+    tuned, other = run("tune")
+    lines = cache.read_text().split("\n")
+    lines = [ln for ln in lines if ln.strip()]
+    assert len(lines) == 1, lines
+    f = lines[0].split()
+    assert len(f) == 9 and f[0].startswith("gfx") and int(f[1]) == 1 and int(f[2]) == 300
+    assert (int(f[6]), int(f[7])) == (tuned["leaf"], tuned["wgs_per_cu"])
+    assert other == {"leaf": 64, "wgs_per_cu": 0}  # untuned signature: the FP32 defaults
+    # a line for the other signature (500 matrices of order 33), same device
+    with open(cache, "a") as fh:
+        fh.write(f"{f[0]} 1 500 {500 * 33} {500 * 33 * 33} 33 32 1 0.5\n")
+    loaded, other = run("read")
+    assert loaded == tuned
+    assert other == {"leaf": 32, "wgs_per_cu": 1}
+    plain, other = run("read", with_cache=False)
+    assert plain == {"leaf": 64, "wgs_per_cu": 0} and other == {"leaf": 64, "wgs_per_cu": 0}
+
+
+@pytest.mark.parametrize("dt,sizes", [("f64", [17, 300, 64, 1024, 129, 5, 256, 33] * 3),
+                                      ("f32", [40, 700, 96, 1] * 6),
+                                      ("f32", [256] * 8)])  # uniform: the level path
+def test_upper_batch(P, dt, sizes):
+    """opts.upper on a packed batch with gaps between matrices: X_i = U_i^-1
+    (upper, zeros below the diagonal); the strict lower parts of the inputs
+    hold NaN and must not be read; the gaps are left untouched."""
+    import torch
+
+    dtype = np.float64 if dt == "f64" else np.float32
+    sizes = np.array(sizes, dtype=np.int32)
+    banner(f"batched upper, {len(sizes)} {dt} matrices")
+    gap = 7
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    for i in range(1, len(sizes)):
+        offs[i] = offs[i - 1] + int(sizes[i - 1]) ** 2 + gap
+    total = int(offs[-1] + int(sizes[-1]) ** 2 + gap)
+    packed = np.full(total, -3.0, dtype=dtype)
+    lowers = []
+    for i, n in enumerate(sizes):
+        L = synth.lower_triangular(int(n), 7000 + i, dtype=dtype)
+        U = np.ascontiguousarray(L.T)
+        U[np.tril_indices(int(n), -1)] = np.nan
+        packed[offs[i]:offs[i] + n * n] = U.ravel()
+        lowers.append(L)
+    Lg = torch.from_numpy(packed).cuda()
+    X = torch.full_like(Lg, 5.0)
+    Xg, st = P.tril_inverse_batched(Lg, sizes, offs, dt, upper=True, out=X)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Xh = Xg.cpu().numpy()
+    for i, n in enumerate(sizes):  # gaps untouched
+        end = offs[i] + n * n
+        assert np.all(Xh[end:end + gap] == 5.0)
+    Xs = [x.T.copy() for x in unpack(Xh, offs, sizes)]  # lower inverses of L_i = U_i^T
+    check(lowers, Xs, TOL[dt], oracle_every=3)
