@@ -131,8 +131,11 @@ enum {
   kEpAccum = 256  // D = alpha acc + D (read before the store)
 };
 
+// Two workgroups per CU (256 registers per lane, 2 x 68 KB of LDS): with one
+// wave per SIMD, each K step's LDS reads and the store of the next step's
+// operands left the matrix core idle; a second resident wave fills those gaps.
 template <typename TI, typename TC, int AT, int BT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EP>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs<TI> a) {
+__global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs<TI> a) {
   typedef Mma<TC> MM;
   __shared__ TC lds[2 * (ABUF + BBUF)];
   __shared__ double red[4];
