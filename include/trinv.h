@@ -258,13 +258,15 @@ typedef struct {
   int32_t wgs_per_cu;   /* resident workgroups per CU (0 = the occupancy limit;
                            0 in autotune output of the level path) */
   float ms;             /* time of one launch pair with it; -1 if not timed */
+  int32_t tile;         /* largest tile of the level products, 64 or 128
+                           (0 = 128): each level uses min(h, tile) squares */
 } trinv_batched_config;
 
 /*
  * Autotuner of trinv_tril_inverse_batched (not in the paper): times the
  * persistent launch with every candidate configuration (leaf in {32, 64},
- * or opts->leaf if set; wgs_per_cu from 1 up to the occupancy limit in powers
- * of two, and that limit) on the caller's buffers and stream, one untimed
+ * or opts->leaf if set; tile in {64, 128}; wgs_per_cu from 1 up to the
+ * occupancy limit in powers of two, and that limit) on the caller's buffers and stream, one untimed
  * launch and the fastest of three each, and keeps the fastest for this
  * batch's order signature (mode, count, sum of n_i, sum of n_i^2, largest n_i)
  * for the rest of the process: later trinv_tril_inverse_batched calls with
@@ -278,7 +280,7 @@ typedef struct {
  * Synchronises `stream` (not for graph capture: tune first, then capture).
  * If the environment variable TRINV_TUNE_CACHE names a file, every result is
  * appended to it as a line "device mode count sum sum_sq largest leaf
- * wgs_per_cu ms" (device: architecture name / CU count), and the first
+ * wgs_per_cu tile ms" (device: architecture name / CU count), and the first
  * lookup of a process loads that file's lines for the current device, so a
  * later process reuses them without tuning (a missing or unreadable file is
  * ignored).
@@ -291,13 +293,14 @@ int trinv_batched_autotune(int mode, int64_t batch, const int32_t *n_host, const
 /* Sets the configuration later trinv_tril_inverse_batched calls use for
  * batches with this order signature (as trinv_batched_autotune would), e.g.
  * one an earlier process found. cfg->leaf 32 or 64, cfg->wgs_per_cu >= 0 (0
- * or above the occupancy limit: that limit); else TRINV_ERR_ARG. */
+ * or above the occupancy limit: that limit), cfg->tile 0, 64 or 128; else
+ * TRINV_ERR_ARG. */
 int trinv_batched_set_config(int mode, int64_t batch, const int32_t *n_host, const trinv_batched_config *cfg);
 
 /* The configuration the next trinv_tril_inverse_batched call with this
  * order signature would use (set, tuned in this process, or loaded from the
- * TRINV_TUNE_CACHE file; otherwise the default leaf and wgs_per_cu = 0);
- * cfg->ms = -1. TRINV_ERR_ARG for batch <= 0, a null pointer or an order
+ * TRINV_TUNE_CACHE file; otherwise the default leaf, wgs_per_cu = 0 and
+ * tile 128); cfg->ms = -1. TRINV_ERR_ARG for batch <= 0, a null pointer or an order
  * outside 1..1024; TRINV_ERR_UNSUPPORTED for modes other than F64 / F32. */
 int trinv_batched_get_config(int mode, int64_t batch, const int32_t *n_host, trinv_batched_config *cfg);
 

@@ -45,7 +45,8 @@ class Opts(ctypes.Structure):
 
 
 class BatchedConfig(ctypes.Structure):
-    _fields_ = [("leaf", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("ms", ctypes.c_float)]
+    _fields_ = [("leaf", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("tile", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

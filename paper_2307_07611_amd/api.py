@@ -243,16 +243,16 @@ def batched_autotune(L_packed: torch.Tensor, sizes, offsets=None, mode=None, *, 
                                     ctypes.byref(o), ws.data_ptr(), ws.numel(), _stream(), ctypes.byref(cfg))
     if st != _lib.OK:
         raise _lib.TrinvError(st, "trinv_batched_autotune")
-    return {"leaf": cfg.leaf, "wgs_per_cu": cfg.wgs_per_cu, "ms": cfg.ms}
+    return {"leaf": cfg.leaf, "wgs_per_cu": cfg.wgs_per_cu, "tile": cfg.tile, "ms": cfg.ms}
 
 
-def batched_set_config(sizes, mode, leaf, wgs_per_cu=0):
+def batched_set_config(sizes, mode, leaf, wgs_per_cu=0, tile=0):
     """Pin the persistent batched launch's configuration for batches with these
     orders (trinv_batched_set_config)."""
     import numpy as np
 
     sizes_np = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
-    cfg = _lib.BatchedConfig(leaf, wgs_per_cu, -1.0)
+    cfg = _lib.BatchedConfig(leaf, wgs_per_cu, -1.0, tile)
     st = _lib.load().trinv_batched_set_config(_lib.MODES[mode], len(sizes_np), sizes_np.ctypes.data,
                                               ctypes.byref(cfg))
     if st != _lib.OK:
@@ -271,7 +271,7 @@ def batched_get_config(sizes, mode) -> dict:
                                               ctypes.byref(cfg))
     if st != _lib.OK:
         raise _lib.TrinvError(st, "trinv_batched_get_config")
-    return {"leaf": cfg.leaf, "wgs_per_cu": cfg.wgs_per_cu}
+    return {"leaf": cfg.leaf, "wgs_per_cu": cfg.wgs_per_cu, "tile": cfg.tile}
 
 
 def skul(A: torch.Tensor, *, want_ainv=True, leaf=0, blocking=True):

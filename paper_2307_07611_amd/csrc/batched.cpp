@@ -79,11 +79,13 @@ WsLevels carve_levels(Carve& c, int mode, int64_t batch, int64_t n, int64_t leaf
 int64_t level_leaf(int mode, int64_t n, int32_t opt_leaf) { return opt_leaf ? opt_leaf : default_leaf(mode, n); }
 
 // Tunable parameters of the persistent launch: the leaf order (the
-// recursion's cut-off: 32 or 64; 0 = the mode's default) and the resident
-// workgroups per CU (0: the occupancy limit).
+// recursion's cut-off: 32 or 64; 0 = the mode's default), the resident
+// workgroups per CU (0: the occupancy limit) and the largest tile of the
+// level products (64 or 128; 0 = 128).
 struct PersistentConfig {
   int leaf = 0;
   int per_cu = 0;
+  int tile = 0;
 };
 
 // Default leaf order: 64 for FP32; 32 for FP64 (a 64-leaf stage of FP64 L^T
@@ -99,7 +101,7 @@ std::map<BatchKey, PersistentConfig> g_tuned;  // autotuner results, per process
 
 // On-disk tuning cache (opt-in): the environment variable TRINV_TUNE_CACHE
 // names a text file of lines "device mode count sum sum_sq largest leaf
-// wgs_per_cu ms", device = the GPU's architecture name and CU count. The
+// wgs_per_cu tile ms", device = the GPU's architecture name and CU count. The
 // lines of the current device are loaded at the first lookup of the process
 // (later lines win); every autotuner result is appended.
 bool g_disk_loaded = false;
@@ -124,13 +126,13 @@ void load_disk_cache_locked() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char t[160];
-  int mode = 0, nmax = 0, leaf = 0, per_cu = 0;
+  int mode = 0, nmax = 0, leaf = 0, per_cu = 0, tile = 0;
   long long batch = 0, s1 = 0, s2 = 0;
   float ms = 0.0f;
-  while (std::fscanf(f, "%159s %d %lld %lld %lld %d %d %d %f", t, &mode, &batch, &s1, &s2, &nmax, &leaf, &per_cu,
-                     &ms) == 9)
-    if (tag == t && (leaf == 32 || leaf == 64) && per_cu >= 0)
-      g_tuned[BatchKey(mode, batch, s1, s2, nmax)] = PersistentConfig{leaf, per_cu};
+  while (std::fscanf(f, "%159s %d %lld %lld %lld %d %d %d %d %f", t, &mode, &batch, &s1, &s2, &nmax, &leaf, &per_cu,
+                     &tile, &ms) == 10)
+    if (tag == t && (leaf == 32 || leaf == 64) && per_cu >= 0 && (tile == 0 || tile == 64 || tile == 128))
+      g_tuned[BatchKey(mode, batch, s1, s2, nmax)] = PersistentConfig{leaf, per_cu, tile};
   std::fclose(f);
 }
 
@@ -141,8 +143,8 @@ void append_disk_cache_locked(const BatchKey& k, const PersistentConfig& c, floa
   if (tag.empty()) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %lld %lld %lld %d %d %d %.4f\n", tag.c_str(), std::get<0>(k), (long long)std::get<1>(k),
-               (long long)std::get<2>(k), (long long)std::get<3>(k), std::get<4>(k), c.leaf, c.per_cu, ms);
+  std::fprintf(f, "%s %d %lld %lld %lld %d %d %d %d %.4f\n", tag.c_str(), std::get<0>(k), (long long)std::get<1>(k),
+               (long long)std::get<2>(k), (long long)std::get<3>(k), std::get<4>(k), c.leaf, c.per_cu, c.tile, ms);
   std::fclose(f);
 }
 
@@ -204,11 +206,14 @@ hipError_t launch_persistent(int mode, int64_t batch, const int32_t* n_dev, cons
                              const void* L_packed, void* X_packed, int32_t* status_dev, const WsPersistent& w,
                              const trinv_opts& o, const PersistentConfig& c, hipStream_t s) {
   const int leaf = o.leaf ? o.leaf : (c.leaf ? c.leaf : default_batched_leaf(mode));
+  const int tile = c.tile ? c.tile : 128;
   if (mode == TRINV_F32)
     return launch_batched<float>(batch, n_dev, off_dev, (const float*)L_packed, (float*)X_packed, status_dev,
-                                 w.order, w.queue, o.unit_diag, batched_grid<float>(batch, leaf, c.per_cu), leaf, s);
+                                 w.order, w.queue, o.unit_diag, batched_grid<float>(batch, leaf, c.per_cu), leaf, tile,
+                                 s);
   return launch_batched<double>(batch, n_dev, off_dev, (const double*)L_packed, (double*)X_packed, status_dev,
-                                w.order, w.queue, o.unit_diag, batched_grid<double>(batch, leaf, c.per_cu), leaf, s);
+                                w.order, w.queue, o.unit_diag, batched_grid<double>(batch, leaf, c.per_cu), leaf, tile,
+                                s);
 }
 
 }  // namespace
@@ -326,7 +331,7 @@ extern "C" int trinv_batched_autotune(int mode, int64_t batch, const int32_t* n_
                                       const int64_t* off_host, const int64_t* off_dev, const void* L_packed,
                                       void* X_packed, int32_t* status_dev, const trinv_opts* opts, void* ws,
                                       size_t ws_bytes, trinv_stream_t stream, trinv_batched_config* out) {
-  if (out) *out = trinv_batched_config{0, 0, -1.0f};
+  if (out) *out = trinv_batched_config{0, 0, -1.0f, 0};
   if (batch < 0 || batch > INT32_MAX) return TRINV_ERR_ARG;
   if (batch == 0) return TRINV_OK;
   const trinv_opts o = resolve_opts(opts);
@@ -345,8 +350,10 @@ extern "C" int trinv_batched_autotune(int mode, int64_t batch, const int32_t* n_
   for (int leaf : {32, 64}) {
     if (o.leaf && leaf != o.leaf) continue;
     const int occ = mode == TRINV_F32 ? batched_occupancy<float>(leaf, nullptr) : batched_occupancy<double>(leaf, nullptr);
-    for (int k = 1; k <= occ; k *= 2) cands.push_back(PersistentConfig{leaf, k});
-    if ((occ & (occ - 1)) != 0) cands.push_back(PersistentConfig{leaf, occ});
+    for (int tile : {64, 128}) {
+      for (int k = 1; k <= occ; k *= 2) cands.push_back(PersistentConfig{leaf, k, tile});
+      if ((occ & (occ - 1)) != 0) cands.push_back(PersistentConfig{leaf, occ, tile});
+    }
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
@@ -390,7 +397,7 @@ extern "C" int trinv_batched_autotune(int mode, int64_t batch, const int32_t* n_
   // leave X and status from the chosen configuration
   HIP_TRY(launch_persistent(mode, batch, n_dev, off_dev, L_packed, X_packed, status_dev, w, o, best, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (out) *out = trinv_batched_config{best.leaf, best.per_cu, best_ms};
+  if (out) *out = trinv_batched_config{best.leaf, best.per_cu, best_ms, best.tile};
   return TRINV_OK;
 }
 
@@ -398,12 +405,14 @@ extern "C" int trinv_batched_set_config(int mode, int64_t batch, const int32_t* 
                                         const trinv_batched_config* cfg) {
   if (batch <= 0 || batch > INT32_MAX || !n_host || !cfg) return TRINV_ERR_ARG;
   if (mode != TRINV_F64 && mode != TRINV_F32) return TRINV_ERR_UNSUPPORTED;
-  if ((cfg->leaf != 32 && cfg->leaf != 64) || cfg->wgs_per_cu < 0) return TRINV_ERR_ARG;
+  if ((cfg->leaf != 32 && cfg->leaf != 64) || cfg->wgs_per_cu < 0 ||
+      (cfg->tile != 0 && cfg->tile != 64 && cfg->tile != 128))
+    return TRINV_ERR_ARG;
   BatchKey key;
   if (!batch_key(mode, batch, n_host, &key)) return TRINV_ERR_ARG;
   std::lock_guard<std::mutex> lock(g_tuned_mu);
   load_disk_cache_locked();
-  g_tuned[key] = PersistentConfig{cfg->leaf, cfg->wgs_per_cu};
+  g_tuned[key] = PersistentConfig{cfg->leaf, cfg->wgs_per_cu, cfg->tile};
   return TRINV_OK;
 }
 
@@ -413,7 +422,7 @@ extern "C" int trinv_batched_get_config(int mode, int64_t batch, const int32_t* 
   BatchKey key;
   if (!batch_key(mode, batch, n_host, &key)) return TRINV_ERR_ARG;
   const PersistentConfig c = tuned_config(key);
-  *cfg = trinv_batched_config{c.leaf ? c.leaf : default_batched_leaf(mode), c.per_cu, -1.0f};
+  *cfg = trinv_batched_config{c.leaf ? c.leaf : default_batched_leaf(mode), c.per_cu, -1.0f, c.tile ? c.tile : 128};
   return TRINV_OK;
 }
 

@@ -188,7 +188,7 @@ hipError_t launch_nonfinite_status(const T* X, int64_t n, int64_t stride, int64_
 template <typename T>
 hipError_t launch_batched(int64_t batch, const int32_t* n_dev, const int64_t* off_dev, const T* L, T* X,
                           int32_t* status, int32_t* order, uint32_t* queue, int unit, int grid, int leaf,
-                          hipStream_t s);
+                          int tmax, hipStream_t s);
 // Device scratch of the allocation-free batched entry point (a file-scope
 // device array, one copy per device): room for the plan of kNoAllocMaxBatch
 // matrices and the queue counter. Returns this device's addresses (looked up

@@ -19,7 +19,8 @@
 //                          up: a band reads only the rows of T at or above
 //                          it, which the bands below it do not write;
 //      then X12 is written as zeros. The products run on 16 x 16 x 4 MFMAs
-//      (FP32 or FP64) in TM x TM workgroup tiles (TM = min(h, 128); each wave
+//      (FP32 or FP64) in TM x TM workgroup tiles (TM = min(h, tmax), tmax 64 or
+//      128 chosen by the autotuner; each wave
 //      owns a TM/2 x TM/2 quarter), K cut to the triangles (T: k >= first
 //      column of the tile; X21: k < end of the band). All tiles of one step
 //      form one stream of K stages through a four-stage LDS ring filled by
@@ -476,14 +477,14 @@ __device__ __forceinline__ bool leaves(const T* __restrict__ L, T* __restrict__ 
 
 // All levels of one matrix (see the file comment).
 template <typename T, int LEAF>
-__device__ __forceinline__ bool levels(const T* __restrict__ L, T* X, int n, char* ring) {
+__device__ __forceinline__ bool levels(const T* __restrict__ L, T* X, int n, char* ring, int tmax) {
   const int tid = threadIdx.x;
   bool nf = false;
   for (int h = LEAF; h < n; h *= 2) {
     const int span = 2 * h;
     const int nmerge = (n - h + span - 1) / span;
     const int hb_last = min(h, n - (nmerge - 1) * span - h);
-    LevelTiles<T> lt{L, X, n, h, nmerge, hb_last, h < 128 ? h : 128, 0};
+    LevelTiles<T> lt{L, X, n, h, nmerge, hb_last, h < tmax ? h : tmax, 0};  // tile min(h, tmax): 32, 64 or 128
     // kind 0: T = C A^-1; kind 1: X21 = -B^-1 T (one call site per tile size)
 #pragma unroll 1
     for (int kind = 0; kind < 2; ++kind) {
@@ -523,7 +524,8 @@ template <typename T, int LEAF>
 __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 2 : 1) void k_batched(int64_t batch, const int32_t* __restrict__ n_dev,
                                                       const int64_t* __restrict__ off_dev, const T* __restrict__ L,
                                                       T* __restrict__ X, int32_t* __restrict__ status,
-                                                      const int32_t* __restrict__ order, uint32_t* queue, int unit) {
+                                                      const int32_t* __restrict__ order, uint32_t* queue, int unit,
+                                                      int tmax) {
   // the leaves' L^T or the product ring (dynamic LDS)
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ int s_item, s_bad;
@@ -547,7 +549,7 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 2 : 1) void k_batched(in
       const T* Lm = L + offu;
       T* Xm = X + offu;
       nf |= leaves<T, LEAF>(Lm, Xm, n, unit, smem, &s_bad);
-      nf |= levels<T, LEAF>(Lm, Xm, n, smem);
+      nf |= levels<T, LEAF>(Lm, Xm, n, smem, tmax);
     }
     nf = __syncthreads_or(nf);
     if (tid == 0) status[m] = (n < 1 || n > 1024) ? -1 : (s_bad != INT_MAX ? s_bad : (nf ? -2 : 0));
@@ -605,9 +607,9 @@ hipError_t set_lds_attr() {
 template <typename T>
 hipError_t launch_batched(int64_t batch, const int32_t* n_dev, const int64_t* off_dev, const T* L, T* X,
                           int32_t* status, int32_t* order, uint32_t* queue, int unit, int grid, int leaf,
-                          hipStream_t s) {
+                          int tmax, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
-  if ((leaf != 32 && leaf != 64) || grid < 1) return hipErrorInvalidValue;
+  if ((leaf != 32 && leaf != 64) || (tmax != 64 && tmax != 128) || grid < 1) return hipErrorInvalidValue;
   hipError_t e = leaf == 64 ? set_lds_attr<T, 64>() : set_lds_attr<T, 32>();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_batched_plan, dim3(1), dim3(1024), 0, s, batch, n_dev, order, queue);
@@ -616,10 +618,10 @@ hipError_t launch_batched(int64_t batch, const int32_t* n_dev, const int64_t* of
   constexpr size_t lds64 = batched_lds_bytes<T, 64>(), lds32 = batched_lds_bytes<T, 32>();
   if (leaf == 64)
     hipLaunchKernelGGL((k_batched<T, 64>), dim3((unsigned)grid), dim3(kThreads), lds64, s, batch, n_dev, off_dev, L,
-                       X, status, order, queue, unit);
+                       X, status, order, queue, unit, tmax);
   else
     hipLaunchKernelGGL((k_batched<T, 32>), dim3((unsigned)grid), dim3(kThreads), lds32, s, batch, n_dev, off_dev, L,
-                       X, status, order, queue, unit);
+                       X, status, order, queue, unit, tmax);
   return hipGetLastError();
 }
 
@@ -655,9 +657,9 @@ int batched_grid(int64_t batch, int leaf, int per_cu) {
 }
 
 template hipError_t launch_batched<float>(int64_t, const int32_t*, const int64_t*, const float*, float*, int32_t*,
-                                          int32_t*, uint32_t*, int, int, int, hipStream_t);
+                                          int32_t*, uint32_t*, int, int, int, int, hipStream_t);
 template hipError_t launch_batched<double>(int64_t, const int32_t*, const int64_t*, const double*, double*, int32_t*,
-                                           int32_t*, uint32_t*, int, int, int, hipStream_t);
+                                           int32_t*, uint32_t*, int, int, int, int, hipStream_t);
 template int batched_occupancy<float>(int, int*);
 template int batched_occupancy<double>(int, int*);
 template int batched_grid<float>(int64_t, int, int);

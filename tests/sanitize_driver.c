@@ -197,7 +197,7 @@ static void abi_cases(void) {
   CHECK(trinv_tril_inverse_batched(TRINV_F32, 3, bad3, P(1 << 20), off3, P(2 << 20), P(1ull << 30), P(1ull << 31),
                                    P(1ull << 32), &o, NULL, 0, NULL) == TRINV_ERR_ARG);
   CHECK(trinv_batched_workspace_bytes(TRINV_F32, 3, n3, &o) >= 3 * 4 + 4);
-  trinv_batched_config cfg = {16, 1, -1.0f};
+  trinv_batched_config cfg = {16, 1, -1.0f, 0};
   CHECK(trinv_batched_set_config(TRINV_F32, 3, n3, &cfg) == TRINV_ERR_ARG);
   (void)st3;
 

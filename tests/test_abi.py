@@ -313,11 +313,13 @@ def test_batched_get_config_host_side(lib):
     bad = np.array([5, 2000, 100], dtype=np.int32)
     assert lib.trinv_batched_get_config(_lib.F32, 3, bad.ctypes.data, ctypes.byref(cfg)) == _lib.ERR_ARG
     assert lib.trinv_batched_get_config(_lib.F32, 3, n.ctypes.data, ctypes.byref(cfg)) == _lib.OK
-    assert (cfg.leaf, cfg.wgs_per_cu, cfg.ms) == (64, 0, -1.0)
+    assert (cfg.leaf, cfg.wgs_per_cu, cfg.ms, cfg.tile) == (64, 0, -1.0, 128)
     assert lib.trinv_batched_get_config(_lib.F64, 3, n.ctypes.data, ctypes.byref(cfg)) == _lib.OK
     assert (cfg.leaf, cfg.wgs_per_cu) == (32, 0)
     # set_config pins a signature for the rest of the process
-    pin = _lib.BatchedConfig(32, 2, -1.0)
+    pin = _lib.BatchedConfig(32, 2, -1.0, 64)
     assert lib.trinv_batched_set_config(_lib.F32, 3, n.ctypes.data, ctypes.byref(pin)) == _lib.OK
     assert lib.trinv_batched_get_config(_lib.F32, 3, n.ctypes.data, ctypes.byref(cfg)) == _lib.OK
-    assert (cfg.leaf, cfg.wgs_per_cu) == (32, 2)
+    assert (cfg.leaf, cfg.wgs_per_cu, cfg.tile) == (32, 2, 64)
+    bad_tile = _lib.BatchedConfig(32, 2, -1.0, 96)
+    assert lib.trinv_batched_set_config(_lib.F32, 3, n.ctypes.data, ctypes.byref(bad_tile)) == _lib.ERR_ARG

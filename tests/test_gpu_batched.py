@@ -216,18 +216,21 @@ def test_uniform_batches(P, dt, n, batch):
 
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-@pytest.mark.parametrize("leaf,per_cu", [(32, 1), (64, 1), (32, 2), (64, 2), (64, 0), (32, 64)])
-def test_pinned_configurations_vs_oracle(P, dt, leaf, per_cu):
+@pytest.mark.parametrize("leaf,per_cu,tile", [(32, 1, 128), (64, 1, 64), (32, 2, 64), (64, 2, 128), (64, 0, 0),
+                                               (32, 64, 64)])
+def test_pinned_configurations_vs_oracle(P, dt, leaf, per_cu, tile):
     """Every configuration the autotuner may choose gives a correct inverse of
-    every matrix: leaves of 32 or 64 (the recursion's cut-off); a workgroup
-    count per CU above the occupancy limit runs at that limit."""
+    every matrix: leaves of 32 or 64 (the recursion's cut-off), level tiles of
+    at most 64 or 128; a workgroup count per CU above the occupancy limit runs
+    at that limit."""
     import torch
 
-    banner(f"batched {dt} pinned leaf={leaf} wgs_per_cu={per_cu}")
+    banner(f"batched {dt} pinned leaf={leaf} wgs_per_cu={per_cu} tile={tile}")
     sizes = np.array(EDGE_SIZES, dtype=np.int32)
     np_dt = np.float32 if dt == "f32" else np.float64
     packed, offs, mats = make_batch(sizes, np_dt, seed0=5000)
-    P.batched_set_config(sizes, dt, leaf, per_cu)
+    P.batched_set_config(sizes, dt, leaf, per_cu, tile)
+    assert P.batched_get_config(sizes, dt) == {"leaf": leaf, "wgs_per_cu": per_cu, "tile": tile or 128}
     L = torch.from_numpy(packed).cuda()
     X, status = P.tril_inverse_batched(L, sizes, offs, dt)
     torch.cuda.synchronize()
@@ -248,7 +251,7 @@ def test_autotune_then_graph_vs_oracle(P):
     g.L.copy_(torch.from_numpy(packed).cuda())
     cfg = g.tune()
     print(f"autotune: {cfg}", flush=True)
-    assert cfg["leaf"] in (32, 64) and cfg["wgs_per_cu"] >= 1 and cfg["ms"] > 0
+    assert cfg["leaf"] in (32, 64) and cfg["tile"] in (64, 128) and cfg["wgs_per_cu"] >= 1 and cfg["ms"] > 0
     check(mats, unpack(g.X.cpu().numpy(), offs, sizes), TOL["f32"], oracle_every=25)
     g.X.zero_()
     g.capture(tune=False)
@@ -272,7 +275,7 @@ def test_autotune_f64_uneven(P):
     cfg = P.batched_autotune(L, sizes, offs, "f64", out=X, status=status)
     torch.cuda.synchronize()
     print(f"autotune: {cfg}", flush=True)
-    assert cfg["leaf"] in (32, 64) and cfg["wgs_per_cu"] >= 1 and cfg["ms"] > 0
+    assert cfg["leaf"] in (32, 64) and cfg["tile"] in (64, 128) and cfg["wgs_per_cu"] >= 1 and cfg["ms"] > 0
     assert int(status.abs().sum()) == 0
     check(mats, unpack(X.cpu().numpy(), offs, sizes), TOL["f64"], oracle_every=5)
     X2, st2 = P.tril_inverse_batched(L, sizes, offs, "f64")
@@ -338,17 +341,18 @@ def test_tune_cache_across_processes(tmp_path):
     lines = [ln for ln in lines if ln.strip()]
     assert len(lines) == 1, lines
     f = lines[0].split()
-    assert len(f) == 9 and f[0].startswith("gfx") and int(f[1]) == 1 and int(f[2]) == 300
-    assert (int(f[6]), int(f[7])) == (tuned["leaf"], tuned["wgs_per_cu"])
-    assert other == {"leaf": 64, "wgs_per_cu": 0}  # untuned signature: the FP32 defaults
+    assert len(f) == 10 and f[0].startswith("gfx") and int(f[1]) == 1 and int(f[2]) == 300
+    assert (int(f[6]), int(f[7]), int(f[8])) == (tuned["leaf"], tuned["wgs_per_cu"], tuned["tile"])
+    default = {"leaf": 64, "wgs_per_cu": 0, "tile": 128}  # FP32 defaults
+    assert other == default  # untuned signature
     # a line for the other signature (500 matrices of order 33), same device
     with open(cache, "a") as fh:
-        fh.write(f"{f[0]} 1 500 {500 * 33} {500 * 33 * 33} 33 32 1 0.5\n")
+        fh.write(f"{f[0]} 1 500 {500 * 33} {500 * 33 * 33} 33 32 1 64 0.5\n")
     loaded, other = run("read")
     assert loaded == tuned
-    assert other == {"leaf": 32, "wgs_per_cu": 1}
+    assert other == {"leaf": 32, "wgs_per_cu": 1, "tile": 64}
     plain, other = run("read", with_cache=False)
-    assert plain == {"leaf": 64, "wgs_per_cu": 0} and other == {"leaf": 64, "wgs_per_cu": 0}
+    assert plain == default and other == default
 
 
 @pytest.mark.parametrize("dt,sizes", [("f64", [17, 300, 64, 1024, 129, 5, 256, 33] * 3),
