@@ -345,11 +345,16 @@ ORACLE_API void oracle_residual_matrix(int64_t n, const double *L, int64_t ldl, 
                                        double *out) {
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t i = 0; i < n; ++i) {
-    for (int64_t j = 0; j < n; ++j) {
-      double s = 0.0;
-      for (int64_t k = 0; k <= i; ++k) s += L[i * ldl + k] * X[k * ldx + j];
-      out[i * n + j] = (i == j ? 1.0 : 0.0) - s;
+    /* row i of L X: every entry sums L(i, k) X(k, j) over k = 0 .. i in
+     * ascending k, one row of X at a time */
+    double *o = out + i * n;
+    for (int64_t j = 0; j < n; ++j) o[j] = 0.0;
+    for (int64_t k = 0; k <= i; ++k) {
+      const double l = L[i * ldl + k];
+      const double *x = X + k * ldx;
+      for (int64_t j = 0; j < n; ++j) o[j] += l * x[j];
     }
+    for (int64_t j = 0; j < n; ++j) o[j] = (i == j ? 1.0 : 0.0) - o[j];
   }
 }
 
