@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "profile.h"
+
 namespace trinv {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));

@@ -13,7 +13,7 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t count) {
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const int64_t blocks = (count + 255) / 256;
-  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, p, v, count);
+  TRINV_LAUNCH(k_fill_u64, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, p, v, count);
   return hipGetLastError();
 }
 
@@ -89,10 +89,10 @@ hipError_t launch_maxabs(const T* A, int64_t n, int64_t lda, int lower, int unit
   if (n <= 0) return hipSuccess;
   const int64_t rpb = (n + npartial - 1) / npartial;
   const int64_t blocks = (n + rpb - 1) / rpb;
-  hipLaunchKernelGGL((k_maxabs<T>), dim3((unsigned)blocks), dim3(256), 0, s, A, n, lda, lower, unit, rpb, partial);
+  TRINV_LAUNCH((k_maxabs<T>), dim3((unsigned)blocks), dim3(256), 0, s, A, n, lda, lower, unit, rpb, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, s, partial, blocks, out);
+  TRINV_LAUNCH(k_reduce_max, dim3(1), dim3(256), 0, s, partial, blocks, out);
   return hipGetLastError();
 }
 template hipError_t launch_maxabs<double>(const double*, int64_t, int64_t, int, int, double*, int64_t, double*,
@@ -100,9 +100,19 @@ template hipError_t launch_maxabs<double>(const double*, int64_t, int64_t, int, 
 template hipError_t launch_maxabs<float>(const float*, int64_t, int64_t, int, int, double*, int64_t, double*,
                                          hipStream_t);
 
+// Thread t adds entries t, t + 256, t + 512, ... in ascending order; the
+// loads are issued 16 at a time so that their latencies overlap.
 __global__ __launch_bounds__(256) void k_reduce_sum(const double* partial, int64_t count, double* out) {
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < count; i += 256) s += partial[i];
+  int64_t i = threadIdx.x;
+  for (; i + 15 * 256 < count; i += 16 * 256) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = partial[i + u * 256];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += v[u];
+  }
+  for (; i < count; i += 256) s += partial[i];
   s = block_sum_256(s);
   if (threadIdx.x == 0) out[0] = s;
 }
@@ -115,12 +125,12 @@ __global__ __launch_bounds__(256) void k_sumsq_vec(const double* v, int64_t coun
 }
 
 hipError_t launch_sumsq_vec(const double* v, int64_t count, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sumsq_vec, dim3(1), dim3(256), 0, s, v, count, out);
+  TRINV_LAUNCH(k_sumsq_vec, dim3(1), dim3(256), 0, s, v, count, out);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_sum(const double* partial, int64_t count, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, partial, count, out);
+  TRINV_LAUNCH(k_reduce_sum, dim3(1), dim3(256), 0, s, partial, count, out);
   return hipGetLastError();
 }
 
@@ -133,7 +143,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   const int64_t count = (int64_t)(bytes / 4);
   if (count <= 0) return hipSuccess;
   const int64_t blocks = (count + 255) / 256;
-  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, (uint32_t*)p,
+  TRINV_LAUNCH(k_zero_u32, dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, (uint32_t*)p,
                      count);
   return hipGetLastError();
 }
@@ -149,7 +159,7 @@ __global__ void k_fold_status(const uint64_t* words, int64_t count, int64_t m, u
 }
 
 hipError_t launch_fold_status(const uint64_t* words, int64_t count, int64_t m, uint64_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(64), 0, s, words, count, m, out);
+  TRINV_LAUNCH(k_fold_status, dim3(1), dim3(64), 0, s, words, count, m, out);
   return hipGetLastError();
 }
 
@@ -169,7 +179,7 @@ hipError_t launch_block_copy(const T* src, int64_t lds, int64_t sstride, T* dst,
                              int64_t m, int64_t nblocks, T alpha, hipStream_t s) {
   if (m <= 0 || nblocks <= 0) return hipSuccess;
   const int64_t total = nblocks * m * m, blocks = (total + 255) / 256;
-  hipLaunchKernelGGL((k_block_copy<T>), dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, src, lds,
+  TRINV_LAUNCH((k_block_copy<T>), dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, src, lds,
                      sstride, dst, ldd, dstride, m, nblocks, alpha);
   return hipGetLastError();
 }
@@ -189,7 +199,7 @@ template <typename T>
 hipError_t launch_set_diag(T* A, int64_t ld, int64_t n, T v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL((k_set_diag<T>), dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, A, ld, n, v);
+  TRINV_LAUNCH((k_set_diag<T>), dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, A, ld, n, v);
   return hipGetLastError();
 }
 template hipError_t launch_set_diag<double>(double*, int64_t, int64_t, double, hipStream_t);
@@ -215,7 +225,7 @@ hipError_t launch_embed(const T* src, int64_t lds, int64_t sstride, int64_t n, T
   if (m <= 0 || nblocks <= 0) return hipSuccess;
   if (n > m) return hipErrorInvalidValue;
   const int64_t total = nblocks * m * m, blocks = (total + 255) / 256;
-  hipLaunchKernelGGL((k_embed<T>), dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, src, lds,
+  TRINV_LAUNCH((k_embed<T>), dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, src, lds,
                      sstride, n, dst, ldd, dstride, m, nblocks);
   return hipGetLastError();
 }
@@ -243,7 +253,7 @@ hipError_t launch_sum_blocks(const T* src, int64_t lds, int64_t stride, int64_t 
                              T* dst, int64_t ldd, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
   const int64_t total = rows * cols, blocks = (total + 255) / 256;
-  hipLaunchKernelGGL((k_sum_blocks<T>), dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, src, lds,
+  TRINV_LAUNCH((k_sum_blocks<T>), dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, src, lds,
                      stride, count, rows, cols, dst, ldd);
   return hipGetLastError();
 }
@@ -260,7 +270,7 @@ __global__ void k_status_to_i32(const uint64_t* first_bad, int32_t* status, int6
 hipError_t launch_status_to_i32(const uint64_t* first_bad, int32_t* status, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const int64_t blocks = (count + 255) / 256;
-  hipLaunchKernelGGL(k_status_to_i32, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, first_bad,
+  TRINV_LAUNCH(k_status_to_i32, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, first_bad,
                      status, count);
   return hipGetLastError();
 }
@@ -271,7 +281,7 @@ hipError_t launch_sumsq(const T* A, int64_t n, int64_t lda, int lower, int unit,
   if (n <= 0) return hipSuccess;
   const int64_t rpb = (n + npartial - 1) / npartial;
   const int64_t blocks = (n + rpb - 1) / rpb;
-  hipLaunchKernelGGL((k_sumsq<T>), dim3((unsigned)blocks), dim3(256), 0, s, A, n, lda, lower, unit, rpb, partial);
+  TRINV_LAUNCH((k_sumsq<T>), dim3((unsigned)blocks), dim3(256), 0, s, A, n, lda, lower, unit, rpb, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_reduce_sum(partial, blocks, out, s);
@@ -300,7 +310,7 @@ template <typename T>
 hipError_t launch_transpose(const T* A, int64_t lda, T* B, int64_t ldb, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const unsigned g = (unsigned)((n + 31) / 32);
-  hipLaunchKernelGGL((k_transpose<T>), dim3(g, g), dim3(256), 0, s, A, lda, B, ldb, n);
+  TRINV_LAUNCH((k_transpose<T>), dim3(g, g), dim3(256), 0, s, A, lda, B, ldb, n);
   return hipGetLastError();
 }
 template hipError_t launch_transpose<double>(const double*, int64_t, double*, int64_t, int64_t, hipStream_t);
@@ -334,7 +344,7 @@ template <typename T>
 hipError_t launch_transpose_inplace(T* A, int64_t lda, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t t = (n + 31) / 32;
-  hipLaunchKernelGGL((k_transpose_inplace<T>), dim3((unsigned)(t * (t + 1) / 2)), dim3(256), 0, s, A, lda, n);
+  TRINV_LAUNCH((k_transpose_inplace<T>), dim3((unsigned)(t * (t + 1) / 2)), dim3(256), 0, s, A, lda, n);
   return hipGetLastError();
 }
 template hipError_t launch_transpose_inplace<double>(double*, int64_t, int64_t, hipStream_t);
@@ -368,7 +378,7 @@ __global__ __launch_bounds__(256) void k_dense_offsets(const int32_t* __restrict
 
 hipError_t launch_dense_offsets(const int32_t* n_dev, int64_t batch, int64_t* off, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dense_offsets, dim3(1), dim3(256), 0, s, n_dev, batch, off);
+  TRINV_LAUNCH(k_dense_offsets, dim3(1), dim3(256), 0, s, n_dev, batch, off);
   return hipGetLastError();
 }
 
@@ -406,7 +416,7 @@ hipError_t launch_transpose_packed(int64_t batch, const int32_t* n_dev, const in
                                    const int64_t* offb, T* B, int64_t capb, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   if (batch > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_transpose_packed<T>), dim3((unsigned)batch, 8), dim3(256), 0, s, n_dev, offa, A, offb, B,
+  TRINV_LAUNCH((k_transpose_packed<T>), dim3((unsigned)batch, 8), dim3(256), 0, s, n_dev, offa, A, offb, B,
                      capb);
   return hipGetLastError();
 }
@@ -430,7 +440,7 @@ template <typename T>
 hipError_t launch_nonfinite(const T* A, int64_t n, int64_t lda, unsigned* flag, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t rpb = (n + 4095) / 4096;
-  hipLaunchKernelGGL((k_nonfinite<T>), dim3((unsigned)((n + rpb - 1) / rpb)), dim3(256), 0, s, A, n, lda, rpb, flag);
+  TRINV_LAUNCH((k_nonfinite<T>), dim3((unsigned)((n + rpb - 1) / rpb)), dim3(256), 0, s, A, n, lda, rpb, flag);
   return hipGetLastError();
 }
 template hipError_t launch_nonfinite<double>(const double*, int64_t, int64_t, unsigned*, hipStream_t);
@@ -453,7 +463,7 @@ hipError_t launch_nonfinite_status(const T* X, int64_t n, int64_t stride, int64_
                                    hipStream_t s) {
   if (n <= 0 || batch <= 0) return hipSuccess;
   const int64_t rpb = (n + 63) / 64;
-  hipLaunchKernelGGL((k_nonfinite_status<T>), dim3((unsigned)((n + rpb - 1) / rpb), (unsigned)batch), dim3(256), 0,
+  TRINV_LAUNCH((k_nonfinite_status<T>), dim3((unsigned)((n + rpb - 1) / rpb), (unsigned)batch), dim3(256), 0,
                      s, X, n, stride, rpb, status);
   return hipGetLastError();
 }

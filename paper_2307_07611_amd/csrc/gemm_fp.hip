@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs<TI> a) {
 // Runtime options -> one of the instantiated configurations.
 template <typename TI, typename TC, int AT, int BT, int AM, int BM, int TILES, int ORDER, int KLO, int KHI, int EP>
 static hipError_t go(const GemmArgs<TI>& a, hipStream_t s, int64_t total) {
-  hipLaunchKernelGGL((k_gemm<TI, TC, AT, BT, AM, BM, TILES, ORDER, KLO, KHI, EP>), dim3((unsigned)total), dim3(256), 0,
+  TRINV_LAUNCH((k_gemm<TI, TC, AT, BT, AM, BM, TILES, ORDER, KLO, KHI, EP>), dim3((unsigned)total), dim3(256), 0,
                      s, a);
   return hipGetLastError();
 }

@@ -457,6 +457,22 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
                       ((((uintptr_t)a.X) | ((uintptr_t)a.L) | (uintptr_t)(a.ldx * 8) | (uintptr_t)(a.ldl * 8)) & 15) == 0;
   double* const dls = (double*)((char*)lds + kEpDiagOff);  // dL[m0 + r], r < 256
   double* const dxs = dls + LT;                            // dX[n0 + c], c < 256
+  // T and X21: alpha and lp_scale are powers of two within the FP32 range
+  // (checked at launch), so the scalings are exact and the low-precision
+  // values round the FP32 accumulator times one FP32 factor (the same value
+  // as rounding the FP64 product), and dividing by lp_scale is multiplying
+  // by its reciprocal.
+  const float alpha_f = (float)alpha, lp_f = (float)(alpha * a.lp_scale);
+  const double inv_scale = 1.0 / a.lp_scale;
+  // X21: the lane's first element (row m0 + wm 128 + 4 (lane / 32), column
+  // n0 + wn 128 + lane % 32) in the FP64 and the low-precision copy
+  double* x21x = nullptr;
+  u16* x21l = nullptr;
+  if constexpr (EPI == kLpEpX21) {
+    const int64_t r0 = m0 + wm * 128 + 4 * (lane >> 5), c0 = n0 + wn * 128 + (lane & 31);
+    x21x = a.X + z * a.x_bstride + r0 * a.ldx + c0;
+    x21l = (u16*)a.Xlp + z * a.xlp_bstride + r0 * a.ldxlp + c0;
+  }
   // direct loads of block b of this wave into slot b % 2: [slot][X, L][32 rows][32 doubles]
   auto fetch = [&](auto BI) __attribute__((always_inline)) {
     constexpr int b = decltype(BI)::value, i = b / 4, j = b % 4, sl = b & 1;
@@ -479,6 +495,85 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
       fetch(std::integral_constant<int, 0>{});
     }
   }
+  // Interior correction tile: the lane's X and R elements through per-lane
+  // base pointers (row m0 + wm 128 + 4 (lane / 32), column n0 + wn 128 +
+  // lane % 32; uniform offsets per element), the diagonal of X for the tile's
+  // rows staged in LDS once, and each block's X and R loads issued one block
+  // ahead into registers (slot b % 2), so that they are in flight while the
+  // previous block is computed and stored.
+  double* cxw = nullptr;
+  const float* crp = nullptr;
+  double cx[2][16];
+  float cr[2][16];
+  auto cload = [&](auto BI) __attribute__((always_inline)) {
+    constexpr int b = decltype(BI)::value, i = b / 4, j = b % 4, sl = b & 1;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int r = i * 32 + 8 * (k >> 2) + (k & 3);
+      cx[sl][k] = cxw[r * a.ldx + j * 32];
+      cr[sl][k] = crp[r * a.ldr + j * 32];
+    }
+  };
+  if constexpr (EPI == kLpEpCorr) {
+    if (full) {
+      const int64_t r0 = m0 + wm * 128 + 4 * (lane >> 5), c0 = n0 + wn * 128 + (lane & 31);
+      cxw = a.X + r0 * a.ldx + c0;
+      crp = R32r + r0 * a.ldr + c0;
+      dls[tid] = dXr[m0 + tid];
+      __syncthreads();
+      cload(std::integral_constant<int, 0>{});
+      __builtin_amdgcn_sched_barrier(0);
+      static_for<0, 16>([&](auto IJ) {
+        constexpr int b = decltype(IJ)::value, i = b / 4, j = b % 4, sl = b & 1;
+        const f32x16 blk = acc[i][j];
+        // the next block's loads stay behind this block's (vector memory
+        // operations complete in order, so waiting for these does not wait
+        // for those)
+        if constexpr (b + 1 < 16) cload(std::integral_constant<int, b + 1>{});
+        __builtin_amdgcn_sched_barrier(0);
+        const int cl = wn * 128 + j * 32 + (lane & 31), rl = wm * 128 + i * 32 + 4 * (lane >> 5);
+        const int64_t col = n0 + cl, rbase = m0 + rl;
+        double xn[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int r = 8 * (k >> 2) + (k & 3);
+          const double v = cx[sl][k] + dls[rl + r] * (double)cr[sl][k] + alpha * (double)blk[k];
+          xn[k] = col <= rbase + r ? v : 0.0;
+          cxw[(i * 32 + r) * a.ldx + j * 32] = xn[k];
+        }
+        if constexpr (!F16) {
+          if (a.Xn_tb_hi) {  // uniform: the next residual's slices of the new X, from these values
+            u16 hi[16], lo[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+              const double v = col < rbase + 8 * (k >> 2) + (k & 3) ? xn[k] : 0.0;  // strictly lower part
+              const __bf16 h = (__bf16)v;
+              const __bf16 l = (__bf16)(v - (double)(float)h);
+              hi[k] = __builtin_bit_cast(u16, h);
+              lo[k] = __builtin_bit_cast(u16, l);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {  // B role: (col, rows row0 .. row0 + 3), 8 contiguous bytes
+              const int64_t e = pb_index(col, rbase + 8 * q, a.kbx);
+              uint2 vh, vl;
+              vh.x = (unsigned)hi[4 * q] | ((unsigned)hi[4 * q + 1] << 16);
+              vh.y = (unsigned)hi[4 * q + 2] | ((unsigned)hi[4 * q + 3] << 16);
+              vl.x = (unsigned)lo[4 * q] | ((unsigned)lo[4 * q + 1] << 16);
+              vl.y = (unsigned)lo[4 * q + 2] | ((unsigned)lo[4 * q + 3] << 16);
+              *(uint2*)((u16*)a.Xn_tb_hi + e) = vh;
+              *(uint2*)((u16*)a.Xn_tb_lo + e) = vl;
+            }
+            if (m0 + wm * 128 + i * 32 == n0 + wn * 128 + j * 32) {  // uniform: a block on the diagonal
+#pragma unroll
+              for (int k = 0; k < 16; ++k)
+                if (rbase + 8 * (k >> 2) + (k & 3) == col) a.dXn[col] = xn[k];
+            }
+          }
+        }
+      });
+      return;
+    }
+  }
   static_for<0, 16>([&](auto IJ) {
       constexpr int i = decltype(IJ)::value / 4, j = decltype(IJ)::value % 4;
       const f32x16 blk = acc[i][j];
@@ -491,21 +586,39 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
         if (EPI == kLpEpT) {
           u16 o[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) o[e] = to_lp<F16>((float)(alpha * (double)blk[4 * q + e]));
+          for (int e = 0; e < 4; ++e) o[e] = to_lp<F16>(blk[4 * q + e] * alpha_f);
           uint2 v;
           v.x = (unsigned)o[0] | ((unsigned)o[1] << 16);
           v.y = (unsigned)o[2] | ((unsigned)o[3] << 16);
           *(uint2*)(lds + (col - n0) * kTrLd + (row0 - m0)) = v;  // transposed tile, stored below
         } else if (EPI == kLpEpX21) {
           u16 o[4];
+          double xo[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int64_t row = row0 + e;
-            const double v = alpha * (double)blk[4 * q + e];
-            o[e] = to_lp<F16>((float)(v * a.lp_scale));
-            if (full || (colok && row < M)) {
-              a.X[z * a.x_bstride + row * a.ldx + col] = a.x_round ? (double)lp_to_f32<F16>(o[e]) / a.lp_scale : v;
-              ((u16*)a.Xlp)[z * a.xlp_bstride + row * a.ldxlp + col] = o[e];
+          for (int e = 0; e < 4; ++e) o[e] = to_lp<F16>(blk[4 * q + e] * lp_f);
+          if (a.x_round) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xo[e] = (double)lp_to_f32<F16>(o[e]) * inv_scale;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xo[e] = alpha * (double)blk[4 * q + e];
+          }
+          // element (i * 32 + 8 q + e, j * 32) of the lane's part: the offset is uniform
+          if (full) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int64_t r = i * 32 + 8 * q + e;
+              x21x[r * a.ldx + j * 32] = xo[e];
+              x21l[r * a.ldxlp + j * 32] = o[e];
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int64_t r = i * 32 + 8 * q + e;
+              if (colok && row0 + e < M) {
+                x21x[r * a.ldx + j * 32] = xo[e];
+                x21l[r * a.ldxlp + j * 32] = o[e];
+              }
             }
           }
           uint2 v;
@@ -806,7 +919,7 @@ static hipError_t go_lp(const LpGemmArgs& a, hipStream_t s, int64_t total) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k, dim3((unsigned)total), dim3(256), lds, s, a);
+  TRINV_LAUNCH(k, dim3((unsigned)total), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
@@ -837,6 +950,13 @@ static hipError_t dispatch_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_
   return hipErrorInvalidValue;
 }
 
+// +-2^e with |e| <= 100: exact in FP32 and far from its overflow and underflow
+static bool pow2_in_f32(double v) {
+  int e = 0;
+  const double m = std::frexp(std::fabs(v), &e);
+  return m == 0.5 && e >= -99 && e <= 101;
+}
+
 hipError_t launch_gemm_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_t s) {
   if (a.bt.nbatch != 1) return hipErrorInvalidValue;
   // per-lane source offsets are 32-bit byte offsets within 256 rows of a
@@ -847,6 +967,11 @@ hipError_t launch_gemm_lp(const LpGemmArgs& a, const LpConfig& c, hipStream_t s)
   if (total <= 0) return hipSuccess;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
   if (c.tiles == kLowerTiles && a.bt.M != a.bt.N) return hipErrorInvalidValue;
+  // T and X21 epilogues scale by powers of two in FP32 (exact) and multiply by
+  // 1 / lp_scale in place of dividing
+  if (c.epi == kLpEpT && !pow2_in_f32(a.alpha)) return hipErrorInvalidValue;
+  if (c.epi == kLpEpX21 && !(pow2_in_f32(a.lp_scale) && pow2_in_f32(a.alpha * a.lp_scale)))
+    return hipErrorInvalidValue;
   return c.f16 ? dispatch_lp<1>(a, c, s, total) : dispatch_lp<0>(a, c, s, total);
 }
 

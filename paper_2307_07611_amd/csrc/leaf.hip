@@ -140,7 +140,7 @@ static hipError_t go_leaf(dim3 grid, hipStream_t s, int64_t n, const T* L, int64
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k, grid, dim3(256), lds, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb,
+  TRINV_LAUNCH(k, grid, dim3(256), lds, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb,
                      per_matrix_status, round_x);
   return hipGetLastError();
 }

@@ -612,15 +612,15 @@ hipError_t launch_batched(int64_t batch, const int32_t* n_dev, const int64_t* of
   if ((leaf != 32 && leaf != 64) || (tmax != 64 && tmax != 128) || grid < 1) return hipErrorInvalidValue;
   hipError_t e = leaf == 64 ? set_lds_attr<T, 64>() : set_lds_attr<T, 32>();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batched_plan, dim3(1), dim3(1024), 0, s, batch, n_dev, order, queue);
+  TRINV_LAUNCH(k_batched_plan, dim3(1), dim3(1024), 0, s, batch, n_dev, order, queue);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   constexpr size_t lds64 = batched_lds_bytes<T, 64>(), lds32 = batched_lds_bytes<T, 32>();
   if (leaf == 64)
-    hipLaunchKernelGGL((k_batched<T, 64>), dim3((unsigned)grid), dim3(kThreads), lds64, s, batch, n_dev, off_dev, L,
+    TRINV_LAUNCH((k_batched<T, 64>), dim3((unsigned)grid), dim3(kThreads), lds64, s, batch, n_dev, off_dev, L,
                        X, status, order, queue, unit, tmax);
   else
-    hipLaunchKernelGGL((k_batched<T, 32>), dim3((unsigned)grid), dim3(kThreads), lds32, s, batch, n_dev, off_dev, L,
+    TRINV_LAUNCH((k_batched<T, 32>), dim3((unsigned)grid), dim3(kThreads), lds32, s, batch, n_dev, off_dev, L,
                        X, status, order, queue, unit, tmax);
   return hipGetLastError();
 }

@@ -1,7 +1,7 @@
-// Launch profiling (measurement helper): when enabled, every kernel launch of
-// the library is bracketed by a pair of HIP events recorded on the launch's
-// own stream, together with the launch's algorithmic flops and bytes. The
-// pairs are resolved (and the GPU waited for) only when the profile is read.
+// Launch profiling (measurement helper): when enabled, every profiled launch
+// scope of the library gets a pair of HIP events carried by its kernel
+// dispatches, together with its algorithmic flops and bytes. The pairs are
+// resolved (and the GPU waited for) only when the profile is read.
 #include "profile.h"
 
 #include <cstring>
@@ -22,6 +22,7 @@ std::mutex g_mu;
 bool g_on = false;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
+thread_local ProfLaunch* tl_scope = nullptr;
 
 hipEvent_t get_event() {
   if (!g_pool.empty()) {
@@ -47,15 +48,28 @@ ProfLaunch::ProfLaunch(const char* cls, double flops, double bytes, hipStream_t 
   r.a = get_event();
   r.b = get_event();
   if (!r.a || !r.b) return;
-  if (hipEventRecord(r.a, s) != hipSuccess) return;
   g_recs.push_back(r);
-  idx_ = (long)g_recs.size() - 1;
+  a_ = r.a;
+  b_ = r.b;
+  outer_ = tl_scope;
+  tl_scope = this;
 }
 
 ProfLaunch::~ProfLaunch() {
-  if (idx_ < 0) return;
-  std::lock_guard<std::mutex> lk(g_mu);
-  if (idx_ < (long)g_recs.size()) (void)hipEventRecord(g_recs[idx_].b, s_);
+  if (!a_) return;
+  tl_scope = outer_;
+  if (launched_ == 0) {  // nothing launched: an empty interval
+    (void)hipEventRecord(a_, s_);
+    (void)hipEventRecord(b_, s_);
+  }
+}
+
+LaunchEvents next_launch_events() {
+  ProfLaunch* p = tl_scope;
+  if (!p) return LaunchEvents{nullptr, nullptr};
+  LaunchEvents e{p->launched_ == 0 ? p->a_ : nullptr, p->b_};
+  ++p->launched_;
+  return e;
 }
 
 }  // namespace trinv

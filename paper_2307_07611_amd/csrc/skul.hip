@@ -166,7 +166,7 @@ hipError_t launch_crout_diag(const T* W, int64_t ldw, int64_t sw, int nb, T* L, 
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_crout_diag<T>, dim3((unsigned)count), dim3(256), lds, s, W, ldw, sw, nb, L, U, ld, slu, K, S,
+  TRINV_LAUNCH(k_crout_diag<T>, dim3((unsigned)count), dim3(256), lds, s, W, ldw, sw, nb, L, U, ld, slu, K, S,
                      ldk, sk, row0, bad);
   return hipGetLastError();
 }

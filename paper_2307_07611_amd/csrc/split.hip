@@ -129,10 +129,10 @@ static hipError_t split_t(const TS* S, int64_t lds, int64_t n, int f16, const Sp
   if (o.sq && !o.dsq) return hipErrorInvalidValue;
   const int64_t blocks = split_tiles(n);
   if (f16)
-    hipLaunchKernelGGL((k_split<1, TS>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, o, diag, unit, strict,
+    TRINV_LAUNCH((k_split<1, TS>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, o, diag, unit, strict,
                        scale);
   else
-    hipLaunchKernelGGL((k_split<0, TS>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, o, diag, unit, strict,
+    TRINV_LAUNCH((k_split<0, TS>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, o, diag, unit, strict,
                        scale);
   return hipGetLastError();
 }
@@ -181,7 +181,7 @@ hipError_t launch_zero_band_pb(void* const* planes, const int* right, int count,
     bp.p[i] = (u16*)planes[i];
     bp.right[i] = right[i];
   }
-  hipLaunchKernelGGL(k_zero_band_pb, dim3((unsigned)((n + 63) / 64), (unsigned)count), dim3(256), 0, s, bp, kb, n,
+  TRINV_LAUNCH(k_zero_band_pb, dim3((unsigned)((n + 63) / 64), (unsigned)count), dim3(256), 0, s, bp, kb, n,
                      band);
   return hipGetLastError();
 }

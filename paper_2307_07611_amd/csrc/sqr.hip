@@ -101,11 +101,11 @@ hipError_t launch_mgs_panel(const T* V, T* Q, T* R, int64_t ld, int64_t n, int64
   if (w <= 0) return hipSuccess;
   if (w > mgs_panel_width(n) || n > 4 * kThreads || p0 + w > n) return hipErrorInvalidValue;
   if (n <= kThreads)
-    hipLaunchKernelGGL((k_mgs_panel<T, 1, 16>), dim3(1), dim3(kThreads), 0, s, V, Q, R, ld, n, p0, w, bad);
+    TRINV_LAUNCH((k_mgs_panel<T, 1, 16>), dim3(1), dim3(kThreads), 0, s, V, Q, R, ld, n, p0, w, bad);
   else if (n <= 2 * kThreads)
-    hipLaunchKernelGGL((k_mgs_panel<T, 2, 8>), dim3(1), dim3(kThreads), 0, s, V, Q, R, ld, n, p0, w, bad);
+    TRINV_LAUNCH((k_mgs_panel<T, 2, 8>), dim3(1), dim3(kThreads), 0, s, V, Q, R, ld, n, p0, w, bad);
   else
-    hipLaunchKernelGGL((k_mgs_panel<T, 4, 8>), dim3(1), dim3(kThreads), 0, s, V, Q, R, ld, n, p0, w, bad);
+    TRINV_LAUNCH((k_mgs_panel<T, 4, 8>), dim3(1), dim3(kThreads), 0, s, V, Q, R, ld, n, p0, w, bad);
   return hipGetLastError();
 }
 
