@@ -50,6 +50,11 @@ def log(msg):
 
 
 def time_path(P, torch, Ld, mode, steps, warmup, leaf):
+    """Warm-up steps; then `steps` untimed steps with every kernel class timed
+    (the per-class breakdown); then the `steps` timed steps, in which only the
+    dominant product class carries timing events (a timed kernel ends with a
+    flush that its completion event needs, a few microseconds that the other
+    kernels are spared)."""
     n = Ld.shape[0]
     X = torch.empty_like(Ld)
     ws = torch.empty(max(P.workspace_bytes(n, mode, leaf=leaf), 1), dtype=torch.uint8, device=Ld.device)
@@ -59,6 +64,15 @@ def time_path(P, torch, Ld, mode, steps, warmup, leaf):
         _, info = P.tril_inverse(Ld, mode, **kw)
         infos.append(info)
     torch.cuda.synchronize()
+    P.profile_select(None)
+    P.profile_enable(True)
+    for _ in range(steps):
+        P.tril_inverse(Ld, mode, **kw)
+    torch.cuda.synchronize()
+    breakdown = P.profile_read()
+    P.profile_enable(False)
+    dom = dominant_class(breakdown)
+    P.profile_select([dom] if dom else None)
     P.profile_enable(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -72,8 +86,9 @@ def time_path(P, torch, Ld, mode, steps, warmup, leaf):
     wall = time.perf_counter() - t0
     prof = P.profile_read()
     P.profile_enable(False)
+    P.profile_select(None)
     ms = start.elapsed_time(stop) / steps
-    return X, ms, wall, prof, infos[-1]
+    return X, ms, wall, prof, breakdown, infos[-1]
 
 
 def sources_hash(dtype):
@@ -104,11 +119,17 @@ def measured_traffic(cls, dtype):
     return None
 
 
-def roofline(prof):
+def dominant_class(prof):
+    """The matrix-core product class with the largest total time."""
     mm = {k: v for k, v in prof.items() if k.split("_", 1)[-1] in MFMA_KINDS and v["launches"]}
-    if not mm:
+    return max(mm.items(), key=lambda kv: kv[1]["total_ms"])[0] if mm else None
+
+
+def roofline(prof):
+    name = dominant_class(prof)
+    if name is None:
         return None
-    name, e = max(mm.items(), key=lambda kv: kv[1]["total_ms"])
+    e = prof[name]
     dtype = name.split("_", 1)[0]
     avg_ms = e["total_ms"] / e["launches"]
     achieved = (e["flops"] / e["launches"]) / (avg_ms * 1e-3) / 1e12
@@ -435,7 +456,7 @@ def main():
         leaf = 128 if n >= 4096 else 64
         log(f"path {path}: warmup {args.warmup}, steps {args.steps}")
         try:
-            X, ms, wall, prof, info = time_path(P, torch, Ld, path, args.steps, args.warmup, leaf)
+            X, ms, wall, prof, breakdown, info = time_path(P, torch, Ld, path, args.steps, args.warmup, leaf)
         except P.TrinvError as e:
             log(f"path {path} unavailable: {e}")
             continue
@@ -449,7 +470,7 @@ def main():
         results[path] = {"ms": ms, "tflops": flops / (ms * 1e-3) / 1e12, "rel_residual": r["rel"],
                          "rel_residual_in_loop": info.get("rel_residual"),
                          "resid_error_est": info.get("resid_error_est"),
-                         "resid_error_bound": info.get("resid_error_bound"), **fe, "profile": prof,
+                         "resid_error_bound": info.get("resid_error_bound"), **fe, "profile": breakdown,
                          "iterations": info.get("iterations"), "roofline": roofline(prof), "wall_s": wall}
         log(f"path {path}: {ms:.3f} ms/step, {results[path]['tflops']:.2f} TFLOP/s, rel residual {r['rel']:.3e}, "
             f"fwd err {fe['fwd_err_sampled_cols']:.3e}, strictly lower {fe['fwd_err_strict']:.3e}")

@@ -441,8 +441,9 @@ int trinv_refine_residual(int mode, int64_t n, const void *L, int64_t ldl, const
 
 /*
  * Measurement helpers (not part of the method). When profiling is enabled,
- * every kernel launch of the library is bracketed by two HIP events recorded
- * on the stream the launch uses, and filed under its kernel class with the
+ * every profiled launch of the library carries two HIP events on its kernel
+ * dispatches (start of the first kernel, end of the last; hipExtLaunchKernel,
+ * on the stream the launch uses), and is filed under its kernel class with the
  * launch's algorithmic flops and bytes (the work the method must do, not the
  * work the tiles execute). trinv_profile_enable(1) starts a new profile
  * (dropping the old one), trinv_profile_enable(0) stops recording.
@@ -460,6 +461,15 @@ typedef struct {
 
 int trinv_profile_enable(int on);
 int trinv_profile_read(trinv_profile_entry *out, int max_entries);
+
+/*
+ * Restricts recording to the kernel classes named in `classes` (host string,
+ * comma-separated, copied; NULL or "" records every class). A timed launch
+ * ends with the writes its completion event needs made visible, which costs
+ * a few microseconds after it; restricting the classes keeps that cost off
+ * the others. Returns TRINV_OK.
+ */
+int trinv_profile_select(const char *classes);
 
 #ifdef __cplusplus
 }

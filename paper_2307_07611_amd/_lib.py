@@ -28,6 +28,7 @@ EXPORTS = [
     "trinv_tril_inverse_backward", "trinv_factored_workspace_bytes", "trinv_factored_inverse",
     "trinv_residual_workspace_bytes", "trinv_residual", "trinv_refine_residual_workspace_bytes",
     "trinv_refine_residual", "trinv_profile_enable", "trinv_profile_read",
+    "trinv_profile_select",
     "trinv_skul_workspace_bytes", "trinv_skul", "trinv_sqr_workspace_bytes", "trinv_sqr",
     "trinv_brsi_workspace_bytes", "trinv_brsi",
 ]
@@ -133,6 +134,8 @@ def load():
     lib.trinv_profile_enable.restype = ctypes.c_int
     lib.trinv_profile_read.argtypes = [ctypes.POINTER(ProfileEntry), ctypes.c_int]
     lib.trinv_profile_read.restype = ctypes.c_int
+    lib.trinv_profile_select.argtypes = [ctypes.c_char_p]
+    lib.trinv_profile_select.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -448,6 +448,12 @@ def profile_enable(on: bool = True) -> None:
     _lib.load().trinv_profile_enable(int(on))
 
 
+def profile_select(classes=None) -> None:
+    """Record only the named kernel classes (an iterable of names; None: all)."""
+    arg = None if not classes else ",".join(classes).encode()
+    _lib.load().trinv_profile_select(arg)
+
+
 def profile_read() -> dict:
     """Per kernel class: launches, total_ms, flops, bytes (waits for the GPU)."""
     lib = _lib.load()

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,7 @@ struct Rec {
 };
 std::mutex g_mu;
 bool g_on = false;
+std::set<std::string> g_select;  // empty: every class
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 thread_local ProfLaunch* tl_scope = nullptr;
@@ -41,6 +43,7 @@ bool profiling_on() { return g_on; }
 ProfLaunch::ProfLaunch(const char* cls, double flops, double bytes, hipStream_t s) : s_(s) {
   if (!g_on) return;
   std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_select.empty() && !g_select.count(cls)) return;
   Rec r;
   r.cls = cls;
   r.flops = flops;
@@ -84,6 +87,23 @@ extern "C" int trinv_profile_enable(int on) {
     g_pool.push_back(r.b);
   }
   g_recs.clear();
+  return TRINV_OK;
+}
+
+extern "C" int trinv_profile_select(const char* classes) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_select.clear();
+  if (!classes) return TRINV_OK;
+  std::string cur;
+  for (const char* p = classes;; ++p) {
+    if (*p == ',' || *p == '\0') {
+      if (!cur.empty()) g_select.insert(cur);
+      cur.clear();
+      if (*p == '\0') break;
+    } else {
+      cur.push_back(*p);
+    }
+  }
   return TRINV_OK;
 }
 

@@ -406,60 +406,73 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       HIP_TRY(launch_split(X, ldx, n, f16, so, dx, 0, 1, sX, s));
       px_stale = false;
     }
+    // The norms of X (first iterate): AUTO needs them to choose the
+    // residual's precision before launching it (one wait); with the
+    // precision fixed by the options they are read in the same wait as the
+    // residual's sums.
+    bool norms_pending = false;
     if (!have_norms) {
       HIP_TRY(launch_reduce_sum(w.split_sq, split_tiles(n), w.scal + 4, s));
       HIP_TRY(launch_reduce_sum(w.split_dsq, split_tiles(n), w.scal + 5, s));
-      double h6[6];
-      HIP_TRY(hipMemcpyAsync(h6, w.scal, sizeof(h6), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      q = norms_from(h6);
-      have_norms = true;
-      if (resid_fp64 < 0)
-        resid_fp64 = (o.resid == TRINV_RESID_SPLIT || resid_est(f16, false, dn, q) <= 0.5 * o.tol) ? 0 : 1;
+      if (o.resid == TRINV_RESID_SPLIT) resid_fp64 = 0;
+      if (resid_fp64 < 0) {
+        double h6[6];
+        HIP_TRY(hipMemcpyAsync(h6, w.scal, sizeof(h6), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        q = norms_from(h6);
+        have_norms = true;
+        resid_fp64 = resid_est(f16, false, dn, q) <= 0.5 * o.tol ? 0 : 1;
+      } else {
+        norms_pending = true;
+      }
     }
     const int nsp = x_hi_exact ? 2 : 3;
-    if (resid_fp64) {
-      GemmArgs<double> gf{};
-      gf.A = {L, ldl, 0, 0};
-      gf.amask = 2;
-      gf.B = {X, ldx, 0, 0};
-      gf.bmask = 2;
-      gf.alpha = 1.0;
-      gf.tiles = kLowerTiles;
-      gf.order = kDiagDesc;
-      gf.klo = kLoN0;
-      gf.khi = kHiM1;
-      gf.bt = bt;
-      gf.refine_resid = 1;
-      gf.Lfull = L;
-      gf.ldl = ldl;
-      gf.Xfull = X;
-      gf.ldx = ldx;
-      gf.dL = w.dL;
-      gf.dX = dx;
-      gf.R32 = w.R32;
-      gf.ldr = n;
-      gf.Rt = nullptr;  // R^T for the correction is cast from R32 below
-      gf.ldrt = 0;
-      gf.lp_is_f16 = f16;
-      gf.tile_sq = w.tile_sq;
-      gf.tile_sqx = w.tile_sqx;
-      {
-        ProfLaunch pl("f64_residual", tri_flops(dn), dn * dn / 2 * (8 * 2 + 8 + 8 + 4 + 2), s);
-        HIP_TRY(launch_gemm<double, double>(gf, s));
+    auto residual = [&](bool fp64) -> hipError_t {
+      if (fp64) {
+        GemmArgs<double> gf{};
+        gf.A = {L, ldl, 0, 0};
+        gf.amask = 2;
+        gf.B = {X, ldx, 0, 0};
+        gf.bmask = 2;
+        gf.alpha = 1.0;
+        gf.tiles = kLowerTiles;
+        gf.order = kDiagDesc;
+        gf.klo = kLoN0;
+        gf.khi = kHiM1;
+        gf.bt = bt;
+        gf.refine_resid = 1;
+        gf.Lfull = L;
+        gf.ldl = ldl;
+        gf.Xfull = X;
+        gf.ldx = ldx;
+        gf.dL = w.dL;
+        gf.dX = dx;
+        gf.R32 = w.R32;
+        gf.ldr = n;
+        gf.Rt = nullptr;  // R^T for the correction is cast from R32 below
+        gf.ldrt = 0;
+        gf.lp_is_f16 = f16;
+        gf.tile_sq = w.tile_sq;
+        gf.tile_sqx = w.tile_sqx;
+        {
+          ProfLaunch pl("f64_residual", tri_flops(dn), dn * dn / 2 * (8 * 2 + 8 + 8 + 4 + 2), s);
+          hipError_t e = launch_gemm<double, double>(gf, s);
+          if (e != hipSuccess) return e;
+        }
+        const int64_t ntf = gemm_tiles(bt, kLowerTiles);
+        hipError_t e = launch_reduce_sum(w.tile_sq, ntf, w.scal + 0, s);
+        if (e != hipSuccess) return e;
+        return launch_reduce_sum(w.tile_sqx, ntf, w.scal + 1, s);
       }
-      const int64_t ntf = gemm_tiles(bt, kLowerTiles);
-      HIP_TRY(launch_reduce_sum(w.tile_sq, ntf, w.scal + 0, s));
-      HIP_TRY(launch_reduce_sum(w.tile_sqx, ntf, w.scal + 1, s));
-    } else {
       // BF16: R^T leaves in the epilogue; FP16: written below, once ||R|| is known
-      HIP_TRY(split_residual(f16, nsp, n, L, ldl, X, ldx, dx, w, sL, sX, w.R32, n, !f16, s));
-    }
+      return split_residual(f16, nsp, n, L, ldl, X, ldx, dx, w, sL, sX, w.R32, n, !f16, s);
+    };
+    HIP_TRY(residual(resid_fp64 == 1));
     // the norms, and after the forward the leaves' zero-pivot index, in one
     // wait for the stream
-    double h[3];
+    double h[6];
     uint64_t bad = ~0ull;
-    HIP_TRY(hipMemcpyAsync(h, w.scal, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h, w.scal, (norms_pending ? 6 : 3) * sizeof(double), hipMemcpyDeviceToHost, s));
     if (iter == 0) HIP_TRY(hipMemcpyAsync(&bad, w.status, sizeof(bad), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (iter == 0) {
@@ -467,6 +480,10 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
         if (info) info->first_bad_index = (int64_t)bad;
         return TRINV_ERR_SINGULAR;
       }
+    }
+    if (norms_pending) {
+      q = norms_from(h);
+      have_norms = true;
     }
     rho = std::sqrt(h[0]) / (std::sqrt(h[2]) * std::sqrt(h[1]));
     const double est = resid_est(f16, resid_fp64 != 0, dn, q);

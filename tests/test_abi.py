@@ -323,3 +323,14 @@ def test_batched_get_config_host_side(lib):
     assert (cfg.leaf, cfg.wgs_per_cu, cfg.tile) == (32, 2, 64)
     bad_tile = _lib.BatchedConfig(32, 2, -1.0, 96)
     assert lib.trinv_batched_set_config(_lib.F32, 3, n.ctypes.data, ctypes.byref(bad_tile)) == _lib.ERR_ARG
+
+
+def test_profile_select_host_side(lib):
+    """Class selection parses a comma-separated list (empty names ignored);
+    NULL restores every class. No launch happens, so the profile stays empty."""
+    assert lib.trinv_profile_select(b"bf16_residual,,f64_level_T,") == 0
+    assert lib.trinv_profile_enable(1) == 0
+    assert lib.trinv_profile_read(None, 0) == 0
+    assert lib.trinv_profile_enable(0) == 0
+    assert lib.trinv_profile_select(None) == 0
+    assert lib.trinv_profile_select(b"") == 0

@@ -215,3 +215,39 @@ def test_bf16_n16384_leaf32_more_corrections(trinv):
     assert r2["rel"] <= tol and info2["rel_residual"] + info2["resid_error_est"] <= tol
     Xg2 = host(X2[:, torch.from_numpy(cols).cuda()])
     assert rel_fro(Xg2, Xo) < 1e-10
+
+
+@pytest.mark.parametrize("mode", ["bf16_refine", "f16_refine"])
+def test_residual_precision_choice(trinv, mode):
+    """AUTO chooses the residual product's precision from the first iterate's
+    norms: with a tolerance below the split product's estimated error it runs
+    exactly as resid="fp64" (bitwise), with a loose one exactly as
+    resid="split" (whose norms are read with the residual's sums)."""
+    import torch
+
+    n = 2048
+    banner(f"residual precision choice {mode} n={n}")
+    Ld = dev(synth.lower_triangular(n, 12))
+
+    def go(resid, tol):
+        X = torch.empty_like(Ld)
+        try:
+            _, info = trinv.tril_inverse(Ld, mode, leaf=128, tol=tol, max_iter=3, resid=resid, out=X,
+                                         return_info=True)
+            st = 0
+        except trinv.TrinvError as e:
+            info, st = e.info or {}, e.code
+        torch.cuda.synchronize()
+        return X, info, st
+
+    tight = 1e-16  # below the split product's estimated error at this order
+    Xa, ia, sa = go("auto", tight)
+    Xf, i_f, sf = go("fp64", tight)
+    print(f"tight: auto status {sa} est {ia.get('resid_error_est')}, fp64 status {sf} est {i_f.get('resid_error_est')}",
+          flush=True)
+    assert sa == sf and torch.equal(Xa, Xf)
+    assert ia.get("resid_error_est") == i_f.get("resid_error_est")
+    Xa, ia, sa = go("auto", 1e-9)
+    Xs, i_s, ss = go("split", 1e-9)
+    assert sa == ss == 0 and torch.equal(Xa, Xs)
+    assert ia["resid_error_est"] == i_s["resid_error_est"]

@@ -174,3 +174,42 @@ def test_residual_helper_n4096_planted(P):
     cols = np.array([0, q, 4095])
     c = oracle.residual_columns(L, Xp, cols)
     assert np.sqrt(c[1]) == pytest.approx(want, rel=1e-6)
+
+
+def test_profile_select_and_dispatch_events(P):
+    """The launch profiler: every class by default, only the selected ones
+    after profile_select; the timed intervals lie inside the step's own time
+    and the results are those of an unprofiled run (bitwise)."""
+    import torch
+
+    banner("launch profiler classes bf16_refine n=2048")
+    n = 2048
+    Ld = dev(synth.lower_triangular(n, 41))
+    kw = dict(resid="split", tol=1e-9)  # every product on BF16 MFMA at this order
+    X0 = P.tril_inverse(Ld, "bf16_refine", **kw)
+    torch.cuda.synchronize()
+    P.profile_select(None)
+    P.profile_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    X1 = P.tril_inverse(Ld, "bf16_refine", **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    every = P.profile_read()
+    P.profile_enable(False)
+    step_ms = e0.elapsed_time(e1)
+    for cls in ("split", "leaf_f64", "bf16_level_T", "bf16_level_X21", "bf16_residual2", "bf16_correction",
+                "bf16_residual"):
+        assert every[cls]["launches"] >= 1, cls
+    assert all(v["total_ms"] > 0.0 for v in every.values())
+    assert sum(v["total_ms"] for v in every.values()) <= step_ms * 1.05
+    P.profile_select(["bf16_residual2", "bf16_level_T"])
+    P.profile_enable(True)
+    X2 = P.tril_inverse(Ld, "bf16_refine", **kw)
+    torch.cuda.synchronize()
+    some = P.profile_read()
+    P.profile_enable(False)
+    P.profile_select(None)
+    assert sorted(some) == ["bf16_level_T", "bf16_residual2"]
+    assert some["bf16_level_T"]["launches"] == every["bf16_level_T"]["launches"]
+    assert torch.equal(X0, X1) and torch.equal(X0, X2)
