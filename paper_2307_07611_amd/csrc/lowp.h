@@ -127,6 +127,13 @@ inline int64_t split_tiles(int64_t n) {
 hipError_t launch_split(const double* S, int64_t lds, int64_t n, int f16, const SplitOut& o, double* diag, int unit,
                         int strict, double scale, hipStream_t s);
 // The same from an FP32 lower-triangular matrix (no diagonal output).
+// The same split (strict, no unit diagonal) of a matrix whose strictly lower
+// values are exactly a row-major low-precision copy divided by the
+// power-of-two `scale` (lp, leading dimension ldlp): those values are read
+// from the copy (2 bytes instead of 8), the diagonal from S. Panel-blocked
+// hi slices only (hi_b, hi_tb); the lo slices of such a matrix are zero.
+hipError_t launch_split_lp_source(const double* S, int64_t lds, const void* lp, int64_t ldlp, int64_t n, int f16,
+                                  const SplitOut& o, double* diag, double scale, hipStream_t s);
 hipError_t launch_split_f32(const float* S, int64_t lds, int64_t n, int f16, const SplitOut& o, double scale,
                             hipStream_t s);
 // Zeros in a band of `band` columns (multiple of 8) beside the tiles the split

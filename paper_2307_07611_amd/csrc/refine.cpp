@@ -393,7 +393,7 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
       sX = pow2_scale(mx, 14);
     }
     if (!x_sliced) {
-      ProfLaunch pl("split", 0.0, dn * dn / 2 * (8 + (x_hi_exact ? 4 : 6)), s);
+      ProfLaunch pl("split", 0.0, dn * dn / 2 * (x_hi_exact ? 2 + 4 : 8 + 6), s);
       SplitOut so{};
       so.hi_b = w.PX;  // A role of the correction
       so.hi_tb = w.PXthi;  // B role of the residual
@@ -403,7 +403,10 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
         so.sq = w.split_sq;
         so.dsq = w.split_dsq;
       }
-      HIP_TRY(launch_split(X, ldx, n, f16, so, dx, 0, 1, sX, s));
+      if (x_hi_exact)  // X0's strictly lower values are its low-precision copy over sX, exactly
+        HIP_TRY(launch_split_lp_source(X, ldx, w.Xb, ldp, n, f16, so, dx, sX, s));
+      else
+        HIP_TRY(launch_split(X, ldx, n, f16, so, dx, 0, 1, sX, s));
       px_stale = false;
     }
     // The norms of X (first iterate): AUTO needs them to choose the

@@ -16,6 +16,11 @@ typedef unsigned short u16;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int F16>
+__device__ __forceinline__ double lp_value(u16 bits) {
+  return F16 ? (double)__builtin_bit_cast(_Float16, bits) : (double)(float)__builtin_bit_cast(__bf16, bits);
+}
+
+template <int F16>
 __device__ __forceinline__ u16 lp_bits(double v, double* back) {
   if (F16) {
     const _Float16 h = (_Float16)v;
@@ -40,9 +45,15 @@ __device__ __forceinline__ u32x4 pack8(const u16 (*t)[66], int r, int c, int tra
 }  // namespace
 
 // Grid: one block per 64 x 64 tile of the lower triangle (tile row it >= tile col jt).
-template <int F16, typename TS>
+// SRC 0: one element of S per load; SRC 2: two consecutive elements of S
+// per load (S aligned to two elements, lds even); LPSRC (SRC 1): the
+// strictly lower values are read from a row-major low-precision copy
+// (value = copy / scale, exactly, for a power-of-two scale) and only the
+// diagonal from S.
+template <int F16, typename TS, int SRC>
 __global__ __launch_bounds__(256) void k_split(const TS* __restrict__ S, int64_t lds, int64_t n, SplitOut o,
-                                               double* __restrict__ diag, int unit, int strict, double scale) {
+                                               double* __restrict__ diag, int unit, int strict, double scale,
+                                               const u16* __restrict__ lp, int64_t ldlp) {
   __shared__ u16 th[64][66];
   __shared__ u16 tl[64][66];
   __shared__ double red[2][4];
@@ -53,7 +64,110 @@ __global__ __launch_bounds__(256) void k_split(const TS* __restrict__ S, int64_t
   const int64_t jt = q - it * (it + 1) / 2;
   const int64_t i0 = it * 64, j0 = jt * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  constexpr int LPSRC = SRC == 1;
+  const double inv = LPSRC ? 1.0 / scale : 1.0;
   double sq = 0.0, dsq = 0.0;
+  if constexpr (LPSRC) {
+    // Strictly lower values: the copy over scale (a power of two: multiplying
+    // by inv divides exactly), so scale v is the copy itself: hi = its bits,
+    // lo = 0. The FP64 diagonal enters the norms and diag only (strict
+    // slices). Two 16-byte loads per thread: row e / 8 of the tile, columns
+    // 8 (e % 8) .. + 7, e = tid, tid + 256 (the copy's rows are padded to at
+    // least n + 8 elements, so a chunk starting below n stays in its row).
+    u32x4 raw[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = (int)threadIdx.x + 256 * u, r = e >> 3, c = (e & 7) * 8;
+      const int64_t i = i0 + r;
+      raw[u] = (i < n && j0 + c < n) ? *(const u32x4*)(lp + i * ldlp + j0 + c) : u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = (int)threadIdx.x + 256 * u, r = e >> 3, c = (e & 7) * 8;
+      const int64_t i = i0 + r;
+      unsigned packed[4];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int64_t j = j0 + c + t;
+        const bool low = i < n && j < i;
+        const u16 bits = low ? (u16)(raw[u][t >> 1] >> (16 * (t & 1))) : (u16)0;
+        const bool dg = i < n && j == i;
+        const double v = low ? lp_value<F16>(bits) * inv : (dg ? (double)S[i * lds + i] : 0.0);
+        sq += v * v;
+        dsq += dg ? v * v : 0.0;
+        if (dg && diag) diag[i] = v;
+        if (t & 1)
+          packed[t >> 1] |= (unsigned)bits << 16;
+        else
+          packed[t >> 1] = bits;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) *(unsigned*)&th[r][c + 2 * t] = packed[t];
+    }
+  } else if constexpr (SRC == 2) {
+    // Eight loads of two consecutive elements per thread, issued together:
+    // row e / 32 of the tile, columns 2 (e % 32) and + 1, e = tid + 256 u
+    // (a pair reaching column n is loaded as its first element alone).
+    typedef TS ts2 __attribute__((ext_vector_type(2)));
+    ts2 raw[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = (int)threadIdx.x + 256 * u, r = e >> 5, c = (e & 31) * 2;
+      const int64_t i = i0 + r, j = j0 + c;
+      if (i < n && j + 1 < n) {
+        raw[u] = *(const ts2*)(S + i * lds + j);
+      } else {
+        raw[u][0] = (i < n && j < n) ? S[i * lds + j] : (TS)0;
+        raw[u][1] = (TS)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = (int)threadIdx.x + 256 * u, r = e >> 5, c = (e & 31) * 2;
+      const int64_t i = i0 + r;
+      u16 h[2] = {0, 0}, l[2] = {0, 0};
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int64_t j = j0 + c + t;
+        if (i < n && j < n) {
+          double v = (j <= i) ? (double)raw[u][t] : 0.0;
+          if (unit && i == j) v = 1.0;
+          sq += v * v;
+          dsq += (i == j) ? v * v : 0.0;
+          if (i == j && diag) diag[i] = v;
+          if (strict && i == j) v = 0.0;  // slices of the strictly lower part
+          v *= scale;
+          double hb;
+          h[t] = lp_bits<F16>(v, &hb);
+          double lb;
+          l[t] = lp_bits<F16>(v - hb, &lb);
+        }
+      }
+      const int64_t j = j0 + c;
+      if (i < n && j < n) {
+        if (o.hi) {
+          u16* d = o.hi + i * o.ldo + j;
+          if (j + 1 < n && (((uintptr_t)d) & 3) == 0) {
+            *(unsigned*)d = (unsigned)h[0] | ((unsigned)h[1] << 16);
+          } else {
+            d[0] = h[0];
+            if (j + 1 < n) d[1] = h[1];
+          }
+        }
+        if (o.lo) {
+          u16* d = o.lo + i * o.ldo + j;
+          if (j + 1 < n && (((uintptr_t)d) & 3) == 0) {
+            *(unsigned*)d = (unsigned)l[0] | ((unsigned)l[1] << 16);
+          } else {
+            d[0] = l[0];
+            if (j + 1 < n) d[1] = l[1];
+          }
+        }
+      }
+      *(unsigned*)&th[r][c] = (unsigned)h[0] | ((unsigned)h[1] << 16);
+      *(unsigned*)&tl[r][c] = (unsigned)l[0] | ((unsigned)l[1] << 16);
+    }
+  } else {
   for (int r = ty; r < 64; r += 4) {
     const int64_t i = i0 + r, j = j0 + tx;
     u16 h = 0, l = 0;
@@ -74,6 +188,7 @@ __global__ __launch_bounds__(256) void k_split(const TS* __restrict__ S, int64_t
     }
     th[r][tx] = h;
     tl[r][tx] = l;
+  }
   }
   if (o.sq) {  // uniform: this tile's sums of squares (fixed order)
     for (int m = 32; m >= 1; m >>= 1) {
@@ -122,29 +237,47 @@ __global__ __launch_bounds__(256) void k_split(const TS* __restrict__ S, int64_t
   }
 }
 
-template <typename TS>
+template <typename TS, int SRC>
 static hipError_t split_t(const TS* S, int64_t lds, int64_t n, int f16, const SplitOut& o, double* diag, int unit,
-                          int strict, double scale, hipStream_t s) {
+                          int strict, double scale, const u16* lp, int64_t ldlp, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (o.sq && !o.dsq) return hipErrorInvalidValue;
   const int64_t blocks = split_tiles(n);
   if (f16)
-    TRINV_LAUNCH((k_split<1, TS>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, o, diag, unit, strict,
-                       scale);
+    TRINV_LAUNCH((k_split<1, TS, SRC>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, o, diag, unit,
+                 strict, scale, lp, ldlp);
   else
-    TRINV_LAUNCH((k_split<0, TS>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, o, diag, unit, strict,
-                       scale);
+    TRINV_LAUNCH((k_split<0, TS, SRC>), dim3((unsigned)blocks), dim3(256), 0, s, S, lds, n, o, diag, unit,
+                 strict, scale, lp, ldlp);
   return hipGetLastError();
+}
+
+// Pairs of elements per load where S is aligned to two elements and lds is even.
+template <typename TS>
+static hipError_t split_any(const TS* S, int64_t lds, int64_t n, int f16, const SplitOut& o, double* diag, int unit,
+                            int strict, double scale, hipStream_t s) {
+  if ((((uintptr_t)S) % (2 * sizeof(TS))) == 0 && lds % 2 == 0)
+    return split_t<TS, 2>(S, lds, n, f16, o, diag, unit, strict, scale, nullptr, 0, s);
+  return split_t<TS, 0>(S, lds, n, f16, o, diag, unit, strict, scale, nullptr, 0, s);
 }
 
 hipError_t launch_split(const double* S, int64_t lds, int64_t n, int f16, const SplitOut& o, double* diag, int unit,
                         int strict, double scale, hipStream_t s) {
-  return split_t<double>(S, lds, n, f16, o, diag, unit, strict, scale, s);
+  return split_any<double>(S, lds, n, f16, o, diag, unit, strict, scale, s);
+}
+
+hipError_t launch_split_lp_source(const double* S, int64_t lds, const void* lp, int64_t ldlp, int64_t n, int f16,
+                                  const SplitOut& o, double* diag, double scale, hipStream_t s) {
+  int e = 0;
+  if (!lp || ldlp < n || !(scale > 0.0) || std::frexp(scale, &e) != 0.5) return hipErrorInvalidValue;
+  if (o.hi || o.lo || o.lo_b || o.lo_tb || o.hi_t || o.lo_t) return hipErrorInvalidValue;  // hi slices only
+  if ((((uintptr_t)lp) & 15) != 0 || ldlp % 8 != 0 || ldlp < n + 8) return hipErrorInvalidValue;  // 16-byte rows
+  return split_t<double, 1>(S, lds, n, f16, o, diag, 0, 1, scale, (const u16*)lp, ldlp, s);
 }
 
 hipError_t launch_split_f32(const float* S, int64_t lds, int64_t n, int f16, const SplitOut& o, double scale,
                             hipStream_t s) {
-  return split_t<float>(S, lds, n, f16, o, nullptr, 0, 0, scale, s);
+  return split_any<float>(S, lds, n, f16, o, nullptr, 0, 0, scale, s);
 }
 
 // Zeros in a band of `band` columns (a multiple of 8) beside the 64 x 64
