@@ -865,7 +865,7 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
       }
     }
   }
-  if (EPI == kLpEpX21) {  // zero the FP64 X12 block: rows n0.., cols m0.. (transposed tile)
+  if (EPI == kLpEpX21 && a.Xmirror) {  // zero the FP64 X12 block: rows n0.., cols m0.. (transposed tile)
     double* Zb = a.Xmirror + z * a.x_bstride;
     const bool al16 = ((((uintptr_t)Zb) | (uintptr_t)(a.ldx * 8)) & 15) == 0 && (m0 & 1) == 0;
     for (int e = 2 * tid; e < LT * LT; e += 512) {

@@ -18,7 +18,8 @@ namespace trinv {
 template <typename T>
 hipError_t launch_leaf(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int64_t stride, int64_t batch,
                        int leaf, int unit, void* Xlp, void* Xlpt, int lp_is_f16, int64_t ldxl, double lp_scale,
-                       uint64_t* first_bad, int per_matrix_status, hipStream_t s, int round_x = 0);
+                       uint64_t* first_bad, int per_matrix_status, hipStream_t s, int round_x = 0,
+                       int zero_upper = 0);
 
 // ---------------------------------------------------------------- tile products
 // A tile product D = alpha * op(A) * op(B) over a set of output tiles

@@ -60,12 +60,34 @@ __global__ __launch_bounds__(256) void k_leaf_inverse(int64_t n, const T* __rest
                                                       T* __restrict__ X, int64_t ldx, int64_t stride,
                                                       int unit, TL* __restrict__ Xlp, TL* __restrict__ Xlpt,
                                                       int64_t ldxl, double lp_scale, int64_t* __restrict__ first_bad,
-                                                      int per_matrix_status, int round_x) {
+                                                      int per_matrix_status, int round_x, int zero_wgs) {
   constexpr int NS = B / 16, LS = B + 1;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   T* Lt = (T*)smem;           // L^T of the leaf: Lt[k * LS + i] = L(i, k), zero outside
   T* rowb = Lt + B * LS;      // two broadcast rows
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  if (zero_wgs > 0 && (int)blockIdx.x >= (int)gridDim.x - zero_wgs) {
+    // The last zero_wgs workgroups write the zeros of X above the leaf blocks
+    // (row i, columns from the next leaf boundary to n - 1), rows w,
+    // w + zero_wgs, ...; they run on the CUs the leaves leave idle.
+    const int w = (int)blockIdx.x - ((int)gridDim.x - zero_wgs);
+    T* Xm = X + (int64_t)blockIdx.y * stride;
+    // FP64 rows start 16-byte aligned (B is even) when X is and ldx is even:
+    // 16-byte stores, the odd last element alone
+    const bool pairs = sizeof(T) == 8 && ((((uintptr_t)Xm) | (uintptr_t)(ldx * 8)) & 15) == 0;
+    for (int64_t i = w; i < n; i += zero_wgs) {
+      T* row = Xm + i * ldx;
+      const int64_t c0 = (i / B + 1) * B;
+      if (pairs) {
+        typedef T t2 __attribute__((ext_vector_type(2)));
+        for (int64_t c = c0 + 2 * tid; c + 1 < n; c += 512) __builtin_nontemporal_store((t2){(T)0, (T)0}, (t2*)(row + c));
+        if (tid == 0 && c0 < n && ((n - c0) & 1)) row[n - 1] = (T)0;
+      } else {
+        for (int64_t c = c0 + tid; c < n; c += 256) row[c] = (T)0;
+      }
+    }
+    return;
+  }
   const int64_t r0 = (int64_t)blockIdx.x * B;
   const int bs = (int)imin64(B, n - r0);
   if (bs <= 0) return;
@@ -131,7 +153,7 @@ __global__ __launch_bounds__(256) void k_leaf_inverse(int64_t n, const T* __rest
 template <typename T, typename TL, int B>
 static hipError_t go_leaf(dim3 grid, hipStream_t s, int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx,
                           int64_t stride, int unit, TL* Xlp, TL* Xlpt, int64_t ldxl, double lp_scale, int64_t* fb,
-                          int per_matrix_status, int round_x) {
+                          int per_matrix_status, int round_x, int zero_wgs) {
   const size_t lds = sizeof(T) * ((size_t)B * (B + 1) + 2 * B);
   auto k = k_leaf_inverse<T, TL, B>;
   static bool attr_set = false;  // per instantiation
@@ -141,23 +163,27 @@ static hipError_t go_leaf(dim3 grid, hipStream_t s, int64_t n, const T* L, int64
     attr_set = true;
   }
   TRINV_LAUNCH(k, grid, dim3(256), lds, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb,
-                     per_matrix_status, round_x);
+               per_matrix_status, round_x, zero_wgs);
   return hipGetLastError();
 }
 
 template <typename T, typename TL>
 static hipError_t launch_leaf_t(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int64_t stride,
                                 int64_t batch, int leaf, int unit, TL* Xlp, TL* Xlpt, int64_t ldxl, double lp_scale,
-                                uint64_t* first_bad, int per_matrix_status, int round_x, hipStream_t s) {
+                                uint64_t* first_bad, int per_matrix_status, int round_x, int zero_upper,
+                                hipStream_t s) {
   const int64_t nleaves = (n + leaf - 1) / leaf;
   if (nleaves <= 0 || batch <= 0) return hipSuccess;
-  dim3 grid((unsigned)nleaves, (unsigned)batch);
+  // zero_upper: extra workgroups zero X above the leaf blocks, on the CUs the
+  // leaves leave idle and then on those they free (one workgroup per CU)
+  const int zw = (zero_upper && nleaves > 1) ? (int)(nleaves >= 256 ? 128 : 512 - nleaves) : 0;
+  dim3 grid((unsigned)(nleaves + zw), (unsigned)batch);
   int64_t* fb = (int64_t*)first_bad;
   switch (leaf) {
-    case 16: return go_leaf<T, TL, 16>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x);
-    case 32: return go_leaf<T, TL, 32>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x);
-    case 64: return go_leaf<T, TL, 64>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x);
-    case 128: return go_leaf<T, TL, 128>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x);
+    case 16: return go_leaf<T, TL, 16>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x, zw);
+    case 32: return go_leaf<T, TL, 32>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x, zw);
+    case 64: return go_leaf<T, TL, 64>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x, zw);
+    case 128: return go_leaf<T, TL, 128>(grid, s, n, L, ldl, X, ldx, stride, unit, Xlp, Xlpt, ldxl, lp_scale, fb, per_matrix_status, round_x, zw);
     default: return hipErrorInvalidValue;
   }
 }
@@ -165,18 +191,19 @@ static hipError_t launch_leaf_t(int64_t n, const T* L, int64_t ldl, T* X, int64_
 template <typename T>
 hipError_t launch_leaf(int64_t n, const T* L, int64_t ldl, T* X, int64_t ldx, int64_t stride, int64_t batch,
                        int leaf, int unit, void* Xlp, void* Xlpt, int lp_is_f16, int64_t ldxl, double lp_scale,
-                       uint64_t* first_bad, int per_matrix_status, hipStream_t s, int round_x) {
+                       uint64_t* first_bad, int per_matrix_status, hipStream_t s, int round_x, int zero_upper) {
   if (round_x && !Xlp) return hipErrorInvalidValue;
   if (Xlp && lp_is_f16)
     return launch_leaf_t<T, _Float16>(n, L, ldl, X, ldx, stride, batch, leaf, unit, (_Float16*)Xlp, (_Float16*)Xlpt,
-                                      ldxl, lp_scale, first_bad, per_matrix_status, round_x, s);
+                                      ldxl, lp_scale, first_bad, per_matrix_status, round_x, zero_upper, s);
   return launch_leaf_t<T, __bf16>(n, L, ldl, X, ldx, stride, batch, leaf, unit, (__bf16*)Xlp, (__bf16*)Xlpt, ldxl,
-                                  lp_scale, first_bad, per_matrix_status, round_x, s);
+                                  lp_scale, first_bad, per_matrix_status, round_x, zero_upper, s);
 }
 
 template hipError_t launch_leaf<double>(int64_t, const double*, int64_t, double*, int64_t, int64_t, int64_t, int,
-                                        int, void*, void*, int, int64_t, double, uint64_t*, int, hipStream_t, int);
+                                        int, void*, void*, int, int64_t, double, uint64_t*, int, hipStream_t, int,
+                                        int);
 template hipError_t launch_leaf<float>(int64_t, const float*, int64_t, float*, int64_t, int64_t, int64_t, int, int,
-                                       void*, void*, int, int64_t, double, uint64_t*, int, hipStream_t, int);
+                                       void*, void*, int, int64_t, double, uint64_t*, int, hipStream_t, int, int);
 
 }  // namespace trinv

@@ -129,7 +129,7 @@ hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, c
     g2.X = X + hA * ldx;
     g2.ldx = ldx;
     g2.x_bstride = stx;
-    g2.Xmirror = X + hA;
+    g2.Xmirror = nullptr;  // X12 blocks: zeroed by the leaf launch (upper triangle outside the leaves)
     g2.Xlp = w.Xb + hA * ldp;
     g2.ldxlp = ldp;
     g2.xlp_bstride = stp;
@@ -359,9 +359,9 @@ int refine_inverse(int mode, int64_t n, const double* L, int64_t ldl, double* X,
   const int x0_exact = 1;
   {  // leaves in FP64, with row-major and transposed low-precision copies
     const double nl = (double)((n + leaf - 1) / leaf), b = (double)leaf;
-    ProfLaunch pl("leaf_f64", nl * b * b * b / 3.0, nl * b * b * (8 + 8 + 4), s);
+    ProfLaunch pl("leaf_f64", nl * b * b * b / 3.0, nl * b * b * (8 + 8 + 4) + dn * dn / 2 * 8, s);
     HIP_TRY(launch_leaf<double>(n, L, ldl, X, ldx, 0, 1, (int)leaf, o.unit_diag, w.Xb, w.Xbt, f16, ldp, sXf,
-                                w.status, 0, s, x0_exact));
+                                w.status, 0, s, x0_exact, 1));
   }
   HIP_TRY(lp_levels(n, X, ldx, leaf, f16, w, sL, sXf, x0_exact, s));
 
