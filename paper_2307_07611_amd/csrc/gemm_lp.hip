@@ -865,21 +865,6 @@ __global__ __launch_bounds__(256) void k_gemm_lp(LpGemmArgs a) {
       }
     }
   }
-  if (EPI == kLpEpX21 && a.Xmirror) {  // zero the FP64 X12 block: rows n0.., cols m0.. (transposed tile)
-    double* Zb = a.Xmirror + z * a.x_bstride;
-    const bool al16 = ((((uintptr_t)Zb) | (uintptr_t)(a.ldx * 8)) & 15) == 0 && (m0 & 1) == 0;
-    for (int e = 2 * tid; e < LT * LT; e += 512) {
-      const int64_t mr = n0 + e / LT, mc = m0 + e % LT;
-      if (mr >= N) continue;
-      double* d = Zb + mr * a.ldx + mc;
-      if (al16 && mc + 2 <= M) {
-        __builtin_nontemporal_store((f64x2){0.0, 0.0}, (f64x2*)d);
-      } else {
-        if (mc < M) d[0] = 0.0;
-        if (mc + 1 < M) d[1] = 0.0;
-      }
-    }
-  }
   if (EPI == kLpEpResid) {
     double(*red)[4] = (double(*)[4])lds;  // free: every wave has left the main loop (its last barrier)
     for (int m = 32; m >= 1; m >>= 1) {

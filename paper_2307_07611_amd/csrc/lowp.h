@@ -11,8 +11,8 @@ namespace trinv {
 // Which fused epilogue a low-precision product runs.
 enum LpEpilogue {
   kLpEpT = 0,      // store alpha*acc transposed (low precision): T for the next product
-  kLpEpX21 = 1,    // X21 = alpha*acc: FP64 X, low-precision row-major and transposed copies,
-                   // zero the FP64 X12 block
+  kLpEpX21 = 1,    // X21 = alpha*acc: FP64 X, low-precision row-major and transposed copies
+                   // (the FP64 X12 block is zeroed by the leaf launch)
   kLpEpResid = 2,  // R = I - L X assembled in FP64 from alpha*acc = N_L N_X (lower tiles):
                    // FP32 R, low-precision transposed R (if Rt is set), per-tile
                    // ||R||^2 and ||X||^2
@@ -40,7 +40,6 @@ struct LpGemmArgs {
   int64_t ldot, ot_bstride;
   double* X;  // kLpEpX21: X21 block base; kLpEpResid / kLpEpCorr: X
   int64_t ldx, x_bstride;
-  double* Xmirror;  // kLpEpX21: X12 block base (FP64 zeros)
   void* Xlp;        // kLpEpX21: row-major low-precision copy of X21
   int64_t ldxlp, xlp_bstride;
   void* Xlpt;  // kLpEpX21: transposed low-precision copy (element (r,c) -> [c][r])

@@ -85,7 +85,7 @@ WsRefine carve_refine(Carve& c, int64_t n, int64_t leaf) {
 
 // Level products of the forward recursion on low-precision MFMA.
 // sL, sX: power-of-two scales of the L and X planes (1 for BF16); T is stored
-// with the scale of X.
+// with the scale of X. X above the leaf blocks is zeroed by the leaf launch.
 hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, const WsRefine& w, double sL,
                      double sX, int x_round, hipStream_t s) {
   const int64_t ldp = w.ldp;
@@ -129,7 +129,6 @@ hipError_t lp_levels(int64_t n, double* X, int64_t ldx, int64_t leaf, int f16, c
     g2.X = X + hA * ldx;
     g2.ldx = ldx;
     g2.x_bstride = stx;
-    g2.Xmirror = nullptr;  // X12 blocks: zeroed by the leaf launch (upper triangle outside the leaves)
     g2.Xlp = w.Xb + hA * ldp;
     g2.ldxlp = ldp;
     g2.xlp_bstride = stp;
